@@ -1,0 +1,200 @@
+"""FP64 CPU oracle for the imaginary-time Schroedinger eigensolver step.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package.  The product library
+(``paper_2006_16935_amd``) never imports it and shares no code with it.
+
+The arithmetic lives in ``itse_oracle.c`` (plain C, FP64, OpenMP over lines);
+this module is ctypes marshalling plus numpy conveniences.  Functions follow
+arXiv:2006.16935:
+
+* ``fft3d`` / ``fft_lines``: the unnormalised FFT / IFFT of section "Kinetic
+  terms" (naive DFT for lengths <= 16, recursive radix-2/3 Cooley-Tukey above);
+* ``kinetic_symbol`` / ``apply_kinetic``: equations HK1, HK2, HK3 on the
+  eigenmode grid of the same section (plus the relativistic analogue of HK1);
+* ``step``: equation iter_proced with the A and B factors of section "The
+  iterative procedure", reflection projections of section "Parity projection",
+  Gram-Schmidt deflation and full-volume normalisation;
+* ``observe``: Rayleigh-quotient energy and the moments listed for the UPDATE
+  flag in section "Basic configuration";
+* ``certify``: residual of an eigenpair of the step map.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "itse_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+KIN_NR_CONT, KIN_NR_LAT, KIN_REL_LAT, KIN_REL_CONT = 1, 2, 3, 4
+CENTER_CELL, CENTER_ORIGIN = 0, 1
+
+OBS_FIELDS = ("energy", "kinetic", "potential", "norm2", "x", "y", "z", "r2", "parity_even")
+
+
+class Lattice(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("a", ctypes.c_double), ("mass", ctypes.c_double),
+                ("dtau", ctypes.c_double), ("kin", ctypes.c_int),
+                ("subtract_rest", ctypes.c_int), ("center", ctypes.c_int)]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_double) for f in OBS_FIELDS]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f in OBS_FIELDS}
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain ISO C99, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        L = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        LP = ctypes.POINTER(Lattice)
+        OP = ctypes.POINTER(Obs)
+        L.orc_fft_lines.argtypes = [ctypes.c_int, ctypes.c_int, dp, ctypes.c_int]
+        L.orc_fft3d.argtypes = [ctypes.c_int, dp, ctypes.c_int]
+        L.orc_kinetic_symbol.argtypes = [LP, dp]
+        L.orc_apply_kinetic.argtypes = [LP, dp, dp]
+        L.orc_observe.argtypes = [LP, ctypes.c_int, dp, dp, OP]
+        L.orc_project.argtypes = [LP, dp, ctypes.c_int, ctypes.c_int]
+        L.orc_orthonormalise.argtypes = [ctypes.c_int, ctypes.c_int, dp]
+        L.orc_step.argtypes = [LP, ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_longlong,
+                               ctypes.c_int, ip, ip, OP]
+        L.orc_certify.argtypes = [LP, dp, dp, dp, dp, dp]
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        for name in ("orc_fft_lines", "orc_fft3d", "orc_kinetic_symbol", "orc_apply_kinetic",
+                     "orc_observe", "orc_project", "orc_orthonormalise", "orc_step",
+                     "orc_certify"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise RuntimeError(f"oracle {what} failed with status {status}")
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def lattice(n, a, mass, dtau=0.0, kin=KIN_NR_CONT, subtract_rest=True, center="cell") -> Lattice:
+    c = center if isinstance(center, int) else (CENTER_CELL if center == "cell" else CENTER_ORIGIN)
+    return Lattice(int(n), float(a), float(mass), float(dtau), int(kin), int(bool(subtract_rest)), c)
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
+
+
+def set_num_threads(t: int):
+    lib().orc_set_num_threads(int(t))
+
+
+def fft_lines(x: np.ndarray, sign: int = -1) -> np.ndarray:
+    """Transform along the last axis of a complex array (unnormalised)."""
+    x = np.ascontiguousarray(x, dtype=np.complex128).copy()
+    length = x.shape[-1]
+    count = x.size // length if length else 0
+    _check(lib().orc_fft_lines(length, count, _dptr(x.view(np.float64)), sign), "fft_lines")
+    return x
+
+
+def fft3d(x: np.ndarray, sign: int = -1) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.complex128).copy()
+    n = x.shape[0]
+    assert x.shape == (n, n, n)
+    _check(lib().orc_fft3d(n, _dptr(x.view(np.float64)), sign), "fft3d")
+    return x
+
+
+def kinetic_symbol(L: Lattice) -> np.ndarray:
+    T = np.empty((L.n,) * 3, dtype=np.float64)
+    _check(lib().orc_kinetic_symbol(ctypes.byref(L), _dptr(T)), "kinetic_symbol")
+    return T
+
+
+def apply_kinetic(L: Lattice, psi: np.ndarray) -> np.ndarray:
+    psi = np.ascontiguousarray(psi, dtype=np.float64)
+    out = np.empty_like(psi)
+    _check(lib().orc_apply_kinetic(ctypes.byref(L), _dptr(psi), _dptr(out)), "apply_kinetic")
+    return out
+
+
+def _stack(states) -> np.ndarray:
+    if isinstance(states, np.ndarray) and states.ndim == 4:
+        return np.ascontiguousarray(states, dtype=np.float64).copy()
+    return np.ascontiguousarray(np.stack([np.asarray(s, dtype=np.float64) for s in states]))
+
+
+def observe(L: Lattice, states, v: np.ndarray):
+    psi = _stack(states)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    k = psi.shape[0]
+    out = (Obs * k)()
+    _check(lib().orc_observe(ctypes.byref(L), k, _dptr(psi), _dptr(v), out), "observe")
+    return [o.as_dict() for o in out]
+
+
+def project(L: Lattice, psi: np.ndarray, sign: int, axes: int = 7) -> np.ndarray:
+    p = np.ascontiguousarray(psi, dtype=np.float64).copy()
+    _check(lib().orc_project(ctypes.byref(L), _dptr(p), int(sign), int(axes)), "project")
+    return p
+
+
+def orthonormalise(states) -> np.ndarray:
+    psi = _stack(states)
+    _check(lib().orc_orthonormalise(psi.shape[1], psi.shape[0], _dptr(psi)), "orthonormalise")
+    return psi
+
+
+def step(L: Lattice, states, v: np.ndarray, nsteps: int, step0: int = 0, ortho_every: int = 1,
+         parity: Optional[Sequence[int]] = None, axes: Optional[Sequence[int]] = None,
+         record: bool = True):
+    """Run `nsteps` steps.  Returns (states [K,N,N,N], observables [nsteps][K] dicts or None)."""
+    psi = _stack(states)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    k = psi.shape[0]
+    ps = (ctypes.c_int * k)(*([int(s) for s in parity] if parity else [0] * k))
+    ax = (ctypes.c_int * k)(*([int(s) for s in axes] if axes else [7] * k))
+    obs = (Obs * (nsteps * k))() if (record and nsteps > 0) else None
+    _check(lib().orc_step(ctypes.byref(L), k, _dptr(psi), _dptr(v), int(nsteps), int(step0),
+                          int(ortho_every), ps, ax, obs), "step")
+    hist = None
+    if obs is not None:
+        hist = [[obs[s * k + i].as_dict() for i in range(k)] for s in range(nsteps)]
+    return psi, hist
+
+
+def certify(L: Lattice, psi: np.ndarray, v: np.ndarray):
+    psi = np.ascontiguousarray(psi, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    lam, res, en = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().orc_certify(ctypes.byref(L), _dptr(psi), _dptr(v), ctypes.byref(lam),
+                             ctypes.byref(res), ctypes.byref(en)), "certify")
+    return {"lambda": lam.value, "resid": res.value, "energy": en.value}
