@@ -1,0 +1,218 @@
+/*
+ * itse: imaginary-time Schroedinger eigensolver on an N^3 periodic lattice,
+ * MI355X (gfx950) HIP implementation.
+ *
+ * The method is that of arXiv:2006.16935 ("The Relativistic Schroedinger
+ * Equation through FFTW 3: An Extension of quantumfdtd"):
+ *
+ *   psi(tau + dtau) = A psi(tau) - B dtau H_K psi(tau)          (equation iter_proced)
+ *   A = (1 - dtau V/2) / (1 + dtau V/2),  B = 1 / (1 + dtau V/2) (section "The iterative procedure")
+ *   H_K psi = IFFT[ T(k) FFT[psi] ] / N^3                       (equations HK1, HK2, HK3)
+ *
+ * with the momenta k_l = 2 pi m_l / N, m_l in (-N/2, N/2] (equation eigenmodes),
+ * normalisation sum |psi|^2 = 1 over the full lattice, projection of lower
+ * states and the parity projections P^(+-) psi = (psi(r) +- psi(-r))/2
+ * (equation parity).
+ *
+ * Conventions for every entry point:
+ *  - Errors: every call returns an itse_status; nothing throws across the ABI.
+ *    On error, itse_last_error() returns a thread-local message.
+ *  - Layout: states and potentials are real N^3 arrays in C order [x1][x2][x3]
+ *    (x3 fastest).  Spectra are N x N x (N/2+1) complex, interleaved (re, im),
+ *    C order [k1][k2][k3] with k3 = 0..N/2.
+ *  - Memory: host pointers (on_device = 0) are read or written synchronously
+ *    during the call.  Device pointers (on_device = 1) are accessed on the
+ *    lattice's stream; the call returns after enqueueing unless stated.  The
+ *    caller keeps ownership of every buffer it passes.  The library owns the
+ *    lattice's device buffers (allocated through the optional allocator at
+ *    create, released at destroy).
+ *  - Asynchrony: work is enqueued on the HIP stream given at create.  Calls
+ *    that return results to the host (observe, history, get_state to host,
+ *    sync) synchronise that stream.
+ *  - Determinism: sums are formed per workgroup and combined in a fixed order;
+ *    a lattice's results do not depend on other work on the GPU or on the
+ *    batch it is stepped in.
+ */
+#ifndef ITSE_H
+#define ITSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ITSE_MAX_STATES 8
+
+typedef enum {
+    ITSE_OK = 0,
+    ITSE_EINVAL = -1,      /* bad argument (size, pointer, enum, state index) */
+    ITSE_ENOMEM = -2,      /* device allocation failed or over an admission budget */
+    ITSE_EUNSTABLE = -3,   /* dtau * max T(k) > 1.95 or 1 + dtau min(V)/2 <= 0 */
+    ITSE_ENONFINITE = -4,  /* a reduction produced NaN or Inf */
+    ITSE_EDEVICE = -5,     /* a HIP runtime call failed */
+    ITSE_ESTATE = -6,      /* call not valid in the object's current state */
+    ITSE_ENOTFOUND = -7    /* no such request / no result yet */
+} itse_status;
+
+/* Kinetic terms (the paper's KINTERM 1..3, plus the relativistic analogue of
+ * H_K^(1) the paper calls straightforward in section "Kinetic terms"). */
+typedef enum {
+    ITSE_KIN_NR_CONT = 1,  /* H_K^(1): sum k_l^2 / (2 A^2 M)                     */
+    ITSE_KIN_NR_LAT = 2,   /* H_K^(2): 4 sum sin^2(k_l/2) / (2 A^2 M)             */
+    ITSE_KIN_REL_LAT = 3,  /* H_K^(3): sqrt(p^2 + M^2), p^2 = 4/A^2 sum sin^2     */
+    ITSE_KIN_REL_CONT = 4  /* sqrt(p^2 + M^2), p^2 = sum k_l^2 / A^2              */
+} itse_kinetic;
+
+typedef enum {
+    ITSE_FP64 = 0,         /* FP64 storage, transforms and sums                    */
+    ITSE_FP32 = 1          /* FP32 storage and transforms, FP64 sums and Gram-     */
+                           /* Schmidt coefficients, FP64 kinetic symbol            */
+} itse_precision;
+
+typedef enum {
+    ITSE_CENTER_CELL = 0,  /* potential centred at the off-grid point (N-1)/2     */
+    ITSE_CENTER_ORIGIN = 1 /* potential centred at site 0 (minimum image)         */
+} itse_center;
+
+typedef enum { ITSE_DTYPE_F32 = 1, ITSE_DTYPE_F64 = 2 } itse_dtype;
+
+/* Lattice description (the paper's NUM, A, MASS, KINTERM, EPS). */
+typedef struct {
+    int n;                   /* points per axis; 8..512 with prime factors 2, 3 only */
+    double a;                /* lattice spacing A > 0                                 */
+    double mass;             /* mass M > 0                                            */
+    double dtau;             /* imaginary-time step EPS > 0                           */
+    int kin;                 /* itse_kinetic                                          */
+    int subtract_rest_mass;  /* relativistic forms: 1 -> sqrt(p^2+M^2) - M            */
+    int precision;           /* itse_precision                                        */
+    int center;              /* itse_center: coordinates of moments and mirror sites  */
+    int nstates;             /* number of states evolved together, 1..ITSE_MAX_STATES */
+} itse_desc;
+
+/* Observables of one state at the start of a step (the paper's UPDATE output). */
+typedef struct {
+    long long step;          /* global step index of the state these describe         */
+    double energy;           /* (<psi|H_K psi> + <psi|V psi>) / <psi|psi>             */
+    double kinetic;          /* <psi|H_K psi> / <psi|psi>                             */
+    double potential;        /* <psi|V psi> / <psi|psi>                               */
+    double norm2;            /* <psi|psi>                                             */
+    double x, y, z, r2;      /* <x1>, <x2>, <x3>, <r^2> about the potential centre    */
+                             /* (filled when moments were requested, else 0)          */
+    double parity_even;      /* weight of P^+ psi: (1 + <psi|P psi>/<psi|psi>)/2      */
+                             /* (filled when moments were requested, else -1)         */
+} itse_obs;
+
+/* Per-lattice step options. */
+typedef struct {
+    int ortho_every;                   /* Gram-Schmidt of state i against states 0..i-1  */
+                                       /* after steps whose global index+1 is a multiple */
+                                       /* of this; 0 = never (normalisation only)         */
+    int moments;                       /* 1: also compute <x>,<y>,<z>,<r^2>, parity weight*/
+    int parity[ITSE_MAX_STATES];       /* per state: 0 none, +1 / -1 reflection projection*/
+    int axes[ITSE_MAX_STATES];         /* reflected axes, bit0 x1, bit1 x2, bit2 x3;      */
+                                       /* 7 = inversion (P^+-), 4 / 2 = INITSYMMETRY x3/x2*/
+} itse_step_opts;
+
+typedef void *(*itse_alloc_fn)(size_t bytes, void *user);
+typedef void (*itse_free_fn)(void *ptr, void *user);
+
+typedef struct itse_lattice itse_lattice;
+typedef struct itse_batch itse_batch;
+typedef struct itse_server itse_server;
+
+/* Thread-local message for the last failing call on this thread. */
+const char *itse_last_error(void);
+const char *itse_version(void);
+
+/* Device bytes a lattice with this description holds (for admission control). */
+size_t itse_footprint_bytes(const itse_desc *desc);
+
+/* Create a lattice.  Checks n (factors 2, 3; 8..512), a, mass, dtau > 0, kin,
+ * nstates, and the stability bound dtau * max_k T(k) <= 1.95 (ITSE_EUNSTABLE).
+ * `hip_stream` (hipStream_t, may be NULL for the null stream) orders all work.
+ * `alloc`/`free_fn` may be NULL (then hipMalloc/hipFree).  States start at 0,
+ * the potential at 0, the step counter at 0. */
+itse_status itse_create(const itse_desc *desc, void *hip_stream, itse_alloc_fn alloc,
+                        itse_free_fn free_fn, void *alloc_user, itse_lattice **out);
+itse_status itse_destroy(itse_lattice *lat);
+itse_status itse_set_stream(itse_lattice *lat, void *hip_stream);
+
+/* Potential V_b of equation iter_proced, N^3 values.  Rejects non-finite values
+ * (ITSE_ENONFINITE, host input only) and 1 + dtau min(V)/2 <= 0 (ITSE_EUNSTABLE,
+ * host input only; device input is checked on the device at the next step). */
+itse_status itse_set_potential(itse_lattice *lat, const void *v, int dtype, int on_device);
+
+/* State i (0-based), N^3 values, any normalisation (the next step normalises). */
+itse_status itse_set_state(itse_lattice *lat, int i, const void *psi, int dtype, int on_device);
+
+/* Current state i, normalised, orthogonalised as of the last step. */
+itse_status itse_get_state(itse_lattice *lat, int i, void *out, int dtype, int on_device);
+
+/* Per-lattice options used by itse_step (opts == NULL) and by batch steps. */
+itse_status itse_set_step_opts(itse_lattice *lat, const itse_step_opts *opts);
+
+/* nsteps applications of the step map to every state, each followed by the
+ * optional reflection projection, then Gram-Schmidt / normalisation
+ * (order: update, projection, Gram-Schmidt in state order, normalise).
+ * Observables of each state at the start of each step are recorded. */
+itse_status itse_step(itse_lattice *lat, int nsteps, const itse_step_opts *opts);
+
+/* Observables of the current states without stepping (no update). */
+itse_status itse_evaluate(itse_lattice *lat, int moments);
+
+/* Latest observables of state i (from the last step or evaluate).  Synchronises. */
+itse_status itse_observe(itse_lattice *lat, int i, itse_obs *out);
+
+/* Observables of the last `count` steps (oldest first), count <= 4096 and
+ * <= steps taken; out holds count * nstates records.  Synchronises. */
+itse_status itse_history(itse_lattice *lat, int count, itse_obs *out);
+
+long long itse_step_count(const itse_lattice *lat);
+
+/* Modified Gram-Schmidt of state i against states 0..i-1, then normalise. */
+itse_status itse_orthogonalise(itse_lattice *lat, int i);
+
+/* P psi_i = (psi_i + sign * psi_i o R)/2 with R reflecting `axes`, then
+ * normalise; *weight (optional) receives ||P psi||^2 / ||psi||^2.  Synchronises. */
+itse_status itse_project_parity(itse_lattice *lat, int i, int sign, int axes, double *weight);
+
+/* H_K psi_i written to `out_device` (N^3 values in the lattice precision). */
+itse_status itse_apply_kinetic(itse_lattice *lat, int i, void *out_device);
+
+/* Unnormalised forward transform FFT[psi_i], half spectrum N x N x (N/2+1)
+ * complex in the lattice precision, written to `out_device`. */
+itse_status itse_spectrum(itse_lattice *lat, int i, void *out_device);
+
+/* FP64 re-evaluation of state i's observables with an FP64 kinetic application
+ * (for FP32 lattices: the energy of the FP32 state without FP32 transform error).
+ * Synchronises. */
+itse_status itse_polish(itse_lattice *lat, int i, itse_obs *out);
+
+/* Wait for all work enqueued for the lattice; reports device-side errors. */
+itse_status itse_sync(itse_lattice *lat);
+
+/* ---- batched stepping: independent lattices stepped together ------------------ */
+/* Lattices of equal (n, precision) share each pass's launch; the whole chunk of
+ * steps for all lattices is captured once into a HIP graph and replayed.  A
+ * lattice's results are bitwise identical to stepping it alone. */
+itse_status itse_batch_create(int count, itse_lattice *const *lats, void *hip_stream,
+                              itse_batch **out);
+itse_status itse_batch_step(itse_batch *b, int nsteps);
+itse_status itse_batch_destroy(itse_batch *b);
+
+/* ---- schedules ------------------------------------------------------------------ */
+/* Time the available transform schedules for (n, precision) on the current
+ * device and keep the fastest for later lattices of that shape.  `json` (optional)
+ * receives a description of the timings.  Results stay deterministic for a
+ * given schedule. */
+itse_status itse_autotune(int n, int precision, void *hip_stream, char *json, size_t json_len);
+itse_status itse_schedule_get(int n, int precision, char *json, size_t json_len);
+itse_status itse_schedule_set(int n, int precision, int variant);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ITSE_H */

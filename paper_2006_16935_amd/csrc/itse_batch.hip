@@ -1,0 +1,261 @@
+// Batched stepping of independent lattices and schedule selection.
+//
+// A batch groups its lattices by (n, precision, schedule); every pass of the
+// step is one launch per group whose grid covers all (lattice, state) jobs of
+// the group.  A chunk of steps for all groups is captured once into a HIP graph
+// (groups on parallel branches) and replayed with a single graph launch.  The
+// per-job computation is the same code with the same workgroup->data mapping as
+// a lone lattice, so results are bitwise identical alone and in a batch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "itse_internal.h"
+#include "itse_runtime.h"
+
+using namespace itse;
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(ITSE_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                  \
+    } while (0)
+
+struct itse_batch {
+    std::vector<itse_lattice *> lats;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    std::vector<hipStream_t> branch;
+    std::vector<Group> groups;
+    std::vector<void *> dev_arrays;
+    hipGraphExec_t graph1 = nullptr, graphN = nullptr;
+    std::vector<hipEvent_t> evs;
+};
+
+// ------------------------------------------------------------------------------------
+// Schedule registry (selected by itse_autotune / itse_schedule_set)
+// ------------------------------------------------------------------------------------
+static std::mutex g_sched_mu;
+static std::map<std::pair<int, int>, int> g_sched;
+
+namespace itse {
+int schedule_variant_for(int n, int prec) {
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    auto it = g_sched.find({n, prec});
+    return it == g_sched.end() ? 0 : it->second;
+}
+}  // namespace itse
+
+extern "C" itse_status itse_schedule_set(int n, int precision, int variant) {
+    if (!prec_supported(n, precision)) return fail(ITSE_EINVAL, "n = %d not supported", n);
+    const int nv = precision == ITSE_FP32 ? Launch<float>::variants(n) : Launch<double>::variants(n);
+    if (variant < 0 || variant >= nv) return fail(ITSE_EINVAL, "variant %d of %d", variant, nv);
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    g_sched[{n, precision}] = variant;
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_schedule_get(int n, int precision, char *json, size_t len) {
+    if (!prec_supported(n, precision)) return fail(ITSE_EINVAL, "n = %d not supported", n);
+    const int v = schedule_variant_for(n, precision);
+    Sched s = prec_schedule(n, precision, v);
+    if (json && len) {
+        snprintf(json, len,
+                 "{\"n\": %d, \"precision\": %d, \"variant\": %d, \"row_pairs\": %d, \"cols_per_wg\": %d, "
+                 "\"wg_rows\": %d, \"wg_cols\": %d}",
+                 n, precision, v, s.rows_rp, s.cols_w, s.nb_rows, s.nb_cols);
+    }
+    return ITSE_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Batches
+// ------------------------------------------------------------------------------------
+static void batch_release(itse_batch *b) {
+    if (b->graph1) (void)hipGraphExecDestroy(b->graph1);
+    if (b->graphN) (void)hipGraphExecDestroy(b->graphN);
+    for (void *p : b->dev_arrays) (void)hipFree(p);
+    for (auto s : b->branch) (void)hipStreamDestroy(s);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (auto e : b->evs) (void)hipEventDestroy(e);
+}
+
+extern "C" itse_status itse_batch_create(int count, itse_lattice *const *lats, void *stream, itse_batch **out) {
+    if (!out || (count > 0 && !lats)) return fail(ITSE_EINVAL, "null argument");
+    if (count <= 0) return fail(ITSE_EINVAL, "empty batch");
+    *out = nullptr;
+    for (int a = 0; a < count; ++a) {
+        if (!lats[a]) return fail(ITSE_EINVAL, "lattice %d is null", a);
+        for (int b = 0; b < a; ++b)
+            if (lats[a] == lats[b]) return fail(ITSE_EINVAL, "lattice %d appears twice", a);
+    }
+    itse_batch *B = new itse_batch();
+    B->stream = (hipStream_t)stream;
+    B->lats.assign(lats, lats + count);
+    auto bail = [&](itse_status st) {
+        batch_release(B);
+        delete B;
+        return st;
+    };
+    // group by (n, precision, variant), keeping input order within a group
+    std::map<std::tuple<int, int, int>, std::vector<itse_lattice *>> by;
+    std::vector<std::tuple<int, int, int>> order;
+    for (auto *L : B->lats) {
+        auto key = std::make_tuple(L->d.n, L->d.precision, L->variant);
+        if (!by.count(key)) order.push_back(key);
+        by[key].push_back(L);
+    }
+    for (auto &key : order) {
+        auto &members = by[key];
+        std::vector<JobRef> jobs, lrefs;
+        for (auto *L : members) {
+            for (int i = 0; i < L->d.nstates; ++i) jobs.push_back(JobRef{L->dev, i, 0});
+            lrefs.push_back(JobRef{L->dev, 0, 0});
+        }
+        JobRef *dj = nullptr, *dl = nullptr;
+        if (hipMalloc(&dj, jobs.size() * sizeof(JobRef)) != hipSuccess ||
+            hipMalloc(&dl, lrefs.size() * sizeof(JobRef)) != hipSuccess)
+            return bail(fail(ITSE_ENOMEM, "batch job arrays"));
+        B->dev_arrays.push_back(dj);
+        B->dev_arrays.push_back(dl);
+        if (hipMemcpy(dj, jobs.data(), jobs.size() * sizeof(JobRef), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(dl, lrefs.data(), lrefs.size() * sizeof(JobRef), hipMemcpyHostToDevice) != hipSuccess)
+            return bail(fail(ITSE_EDEVICE, "batch job upload"));
+        Group g;
+        g.n = std::get<0>(key);
+        g.prec = std::get<1>(key);
+        g.variant = std::get<2>(key);
+        g.jobs = dj;
+        g.njobs = (int)jobs.size();
+        g.lats = dl;
+        g.nlats = (int)lrefs.size();
+        B->groups.push_back(g);
+    }
+    if (hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(ITSE_EDEVICE, "stream create"));
+    const int nbr = (int)std::min<size_t>(B->groups.size(), 8);
+    for (int i = 0; i < nbr; ++i) {
+        hipStream_t s;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(ITSE_EDEVICE, "stream create"));
+        B->branch.push_back(s);
+    }
+    *out = B;
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_batch_step(itse_batch *B, int nsteps) {
+    if (!B) return fail(ITSE_EINVAL, "null batch");
+    if (nsteps < 0) return fail(ITSE_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return ITSE_OK;
+    // order after earlier work on each lattice's own stream
+    for (auto *L : B->lats) {
+        if (L->stream == B->stream) continue;
+        hipEvent_t ev;
+        HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(ev, L->stream));
+        HIPCHK(hipStreamWaitEvent(B->stream, ev, 0));
+        HIPCHK(hipEventDestroy(ev));
+    }
+    const int chunk = ITSE_GRAPH_CHUNK;
+    if (nsteps >= chunk && !B->graphN) {
+        itse_status st = capture_steps(B->cap, B->groups, chunk, B->branch, &B->graphN);
+        if (st) return st;
+    }
+    if (!B->graph1) {
+        itse_status st = capture_steps(B->cap, B->groups, 1, B->branch, &B->graph1);
+        if (st) return st;
+    }
+    int left = nsteps;
+    while (left >= chunk) {
+        HIPCHK(hipGraphLaunch(B->graphN, B->stream));
+        left -= chunk;
+    }
+    while (left-- > 0) HIPCHK(hipGraphLaunch(B->graph1, B->stream));
+    hipEvent_t done;
+    HIPCHK(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(done, B->stream));
+    for (auto *L : B->lats) {
+        if (L->stream != B->stream) HIPCHK(hipStreamWaitEvent(L->stream, done, 0));
+        L->steps_host += nsteps;
+    }
+    HIPCHK(hipEventDestroy(done));
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_batch_destroy(itse_batch *B) {
+    if (!B) return ITSE_OK;
+    (void)hipStreamSynchronize(B->stream);
+    batch_release(B);
+    delete B;
+    return ITSE_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Autotuning: time every schedule variant for (n, precision) on a scratch lattice.
+// ------------------------------------------------------------------------------------
+extern "C" itse_status itse_autotune(int n, int precision, void *stream, char *json, size_t len) {
+    if (!prec_supported(n, precision)) return fail(ITSE_EINVAL, "n = %d not supported", n);
+    const int nv = precision == ITSE_FP32 ? Launch<float>::variants(n) : Launch<double>::variants(n);
+    std::string rep = "{\"n\": " + std::to_string(n) + ", \"precision\": " + std::to_string(precision) +
+                      ", \"times_ms\": [";
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int v = 0; v < nv; ++v) {
+        {
+            std::lock_guard<std::mutex> lk(g_sched_mu);
+            g_sched[{n, precision}] = v;
+        }
+        itse_desc d{};
+        d.n = n;
+        d.a = 0.1;
+        d.mass = 1.0;
+        d.kin = ITSE_KIN_REL_LAT;
+        d.subtract_rest_mass = 1;
+        d.dtau = 0.025;
+        d.precision = precision;
+        d.center = ITSE_CENTER_ORIGIN;
+        d.nstates = 1;
+        itse_lattice *L = nullptr;
+        itse_status st = itse_create(&d, stream, nullptr, nullptr, nullptr, &L);
+        if (st) return st;
+        std::vector<double> psi((size_t)n * n * n, 1.0);
+        st = itse_set_state(L, 0, psi.data(), ITSE_DTYPE_F64, 0);
+        if (!st) st = itse_step(L, 3, nullptr);
+        hipEvent_t e0, e1;
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        (void)hipEventRecord(e0, (hipStream_t)stream);
+        const int reps = n >= 192 ? 10 : 30;
+        if (!st) st = itse_step(L, reps, nullptr);
+        (void)hipEventRecord(e1, (hipStream_t)stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        itse_destroy(L);
+        if (st) return st;
+        ms /= reps;
+        rep += (v ? ", " : "") + std::to_string(ms);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_sched_mu);
+        g_sched[{n, precision}] = best;
+    }
+    rep += "], \"best\": " + std::to_string(best) + "}";
+    if (json && len) snprintf(json, len, "%s", rep.c_str());
+    return ITSE_OK;
+}

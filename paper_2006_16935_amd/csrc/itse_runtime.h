@@ -1,0 +1,63 @@
+// Host-side runtime structures shared by the runtime translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "itse_internal.h"
+
+#define ITSE_GRAPH_CHUNK 16
+
+namespace itse {
+
+// A set of jobs of equal (n, precision, schedule) stepped by the same launches.
+struct Group {
+    int n = 0, prec = 0, variant = 0;
+    const JobRef *jobs = nullptr;  // device array of (lattice, state)
+    int njobs = 0;
+    const JobRef *lats = nullptr;  // device array of (lattice, 0)
+    int nlats = 0;
+};
+
+itse_status fail(itse_status st, const char *fmt, ...);
+hipError_t enqueue_step(const Group &g, hipStream_t s);
+hipError_t enqueue_eval(const Group &g, hipStream_t s);
+itse_status capture_steps(hipStream_t cap, const std::vector<Group> &groups, int nsteps,
+                          std::vector<hipStream_t> &branch, hipGraphExec_t *out);
+bool prec_supported(int n, int prec);
+Sched prec_schedule(int n, int prec, int variant);
+int schedule_variant_for(int n, int prec);
+double max_symbol(const itse_desc &d);
+itse_status norm_host(itse_lattice *L, int i, double *out);
+hipError_t launch_check_potential(const LatDev *lat, int prec, hipStream_t s);
+
+}  // namespace itse
+
+struct itse_lattice {
+    itse_desc d{};
+    hipStream_t stream = nullptr;
+    itse_alloc_fn alloc = nullptr;
+    itse_free_fn freefn = nullptr;
+    void *alloc_user = nullptr;
+    std::vector<void *> allocations;
+    itse::LatDev host{};            // host mirror of the device record
+    itse::LatDev *dev = nullptr;    // device record
+    itse::JobRef *jobs_dev = nullptr;  // [MAXK] (lattice, state i)
+    itse::JobRef *lat_dev = nullptr;   // [1] (lattice, 0)
+    void **phi_ptrs_dev = nullptr;     // [MAXK] phi buffers (materialisation targets)
+    void **tmp_ptrs_dev = nullptr;     // [MAXK] all pointing at tmp
+    void *tmp = nullptr;               // N^3 scratch in the lattice precision
+    void *staging = nullptr;
+    size_t staging_bytes = 0;
+    itse::Sched sched{};
+    int variant = 0;
+    long long steps_host = 0;
+    itse_step_opts opts{};
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph1 = nullptr;
+    hipGraphExec_t graphN = nullptr;
+    itse_lattice *shadow = nullptr;    // FP64 twin for polish
+    void *stage_buf(size_t bytes);
+    ~itse_lattice();
+};

@@ -1,0 +1,1032 @@
+// Host runtime of the imaginary-time eigensolver: lattice objects, the C ABI of
+// include/itse.h, the finalisation kernel (fixed-order FP64 sums, Gram-Schmidt
+// coefficients by Cholesky of the Gram matrix), step sequencing, HIP graph
+// capture and batched stepping of many lattices.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "itse_internal.h"
+#include "itse_runtime.h"
+
+using namespace itse;
+
+// ------------------------------------------------------------------------------------
+// Errors
+// ------------------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+namespace itse {
+itse_status fail(itse_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+}  // namespace itse
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(ITSE_EDEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                  \
+    } while (0)
+
+extern "C" const char *itse_last_error(void) { return g_err.c_str(); }
+extern "C" const char *itse_version(void) { return "itse 0.1 (gfx950)"; }
+
+// ------------------------------------------------------------------------------------
+// Finalisation kernel: one workgroup per lattice.
+// ------------------------------------------------------------------------------------
+namespace itse {
+
+__device__ double fixed_sum(const double *p, int count, int stride, double *red) {
+    const int tid = threadIdx.x;
+    double acc = 0.0;
+    for (int b = tid; b < count; b += NT) acc += p[(size_t)b * stride];
+    red[tid] = acc;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(NT) k_finalize(const JobRef *__restrict__ lats, int mode) {
+    constexpr int NG = MAXK * (MAXK + 1) / 2;
+    __shared__ double red[NT];
+    __shared__ double rows[MAXK][NQR];
+    __shared__ double cols[MAXK][NQC];
+    __shared__ double proj[MAXK];
+    __shared__ double gram[NG];
+    LatDev &L = *lats[blockIdx.x].lat;
+    const int K = L.nstates;
+    const bool ortho_step = (mode == FIN_STEP) && K > 1 && L.ortho_every > 0 &&
+                            ((L.step + 1) % L.ortho_every) == 0;
+    for (int i = 0; i < K; ++i) {
+        for (int q = 0; q < NQR; ++q) {
+            const double s = fixed_sum(L.part_rows + (size_t)i * L.nb_rows * NQR + q, L.nb_rows, NQR, red);
+            if (threadIdx.x == 0) rows[i][q] = s;
+        }
+        if (L.moments) {
+            for (int q = 0; q < NQC; ++q) {
+                const double s = fixed_sum(L.part_cols + (size_t)i * L.nb_cols * NQC + q, L.nb_cols, NQC, red);
+                if (threadIdx.x == 0) cols[i][q] = s;
+            }
+        }
+        if (mode == FIN_STEP && L.psign[i] != 0) {
+            const double s = fixed_sum(L.part_proj + (size_t)i * L.nb_proj, L.nb_proj, 1, red);
+            if (threadIdx.x == 0) proj[i] = s;
+        }
+    }
+    if (ortho_step) {
+        for (int l = 0, g = 0; l < K; ++l)
+            for (int j = 0; j <= l; ++j, ++g) {
+                const int slot = l * (l + 1) / 2 + j;
+                const double s = fixed_sum(L.part_gram + slot, L.nb_gram, NG, red);
+                if (threadIdx.x == 0) gram[slot] = s;
+                (void)g;
+            }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    int err = 0;
+    // observables of the states at the start of the step
+    for (int i = 0; i < K; ++i) {
+        ObsDev o;
+        const double pp = rows[i][RQ_PP];
+        o.step = L.step;
+        o.norm2 = pp;
+        o.kinetic = rows[i][RQ_PK] / pp;
+        o.potential = rows[i][RQ_VPP] / pp;
+        o.energy = (rows[i][RQ_PK] + rows[i][RQ_VPP]) / pp;
+        if (L.moments) {
+            o.x = rows[i][RQ_X] / pp;
+            o.y = rows[i][RQ_Y] / pp;
+            o.z = rows[i][RQ_Z] / pp;
+            o.r2 = rows[i][RQ_R2] / pp;
+            o.parity_even = 0.5 * (1.0 + cols[i][CQ_PAR] / cols[i][CQ_NORM]);
+        } else {
+            o.x = o.y = o.z = o.r2 = 0.0;
+            o.parity_even = -1.0;
+        }
+        if (!isfinite(o.energy) || !isfinite(pp) || pp <= 0.0) err |= 1;
+        L.obs[i] = o;
+        if (mode == FIN_STEP && L.hist) L.hist[(size_t)(L.step % HIST_CAP) * MAXK + i] = o;
+    }
+    if (mode != FIN_STEP) {
+        if (err) L.error |= err;
+        return;
+    }
+    // coefficients of the new states in terms of the raw updated arrays
+    double M[MAXK][MAXK];
+    for (int j = 0; j < MAXK; ++j)
+        for (int i = 0; i < MAXK; ++i) M[j][i] = 0.0;
+    bool done = false;
+    if (ortho_step) {
+        // G = R^T R (R upper); new states = U R^{-1}
+        double Rm[MAXK][MAXK];
+        bool ok = true;
+        for (int j = 0; j < K && ok; ++j) {
+            for (int i = j; i < K; ++i) {
+                double s = gram[i * (i + 1) / 2 + j];
+                for (int l = 0; l < j; ++l) s -= Rm[l][j] * Rm[l][i];
+                if (i == j) {
+                    if (!(s > 0.0) || !isfinite(s)) {
+                        ok = false;
+                        break;
+                    }
+                    Rm[j][j] = sqrt(s);
+                } else {
+                    Rm[j][i] = s / Rm[j][j];
+                }
+            }
+        }
+        if (ok) {
+            for (int i = 0; i < K; ++i) {
+                M[i][i] = 1.0 / Rm[i][i];
+                for (int j = i - 1; j >= 0; --j) {
+                    double s = 0.0;
+                    for (int l = j + 1; l <= i; ++l) s += Rm[j][l] * M[l][i];
+                    M[j][i] = -s / Rm[j][j];
+                }
+            }
+            done = true;
+        } else {
+            err |= 2;
+        }
+    }
+    if (!done) {
+        for (int i = 0; i < K; ++i) {
+            const double nn = L.psign[i] != 0 ? proj[i] : rows[i][RQ_UU];
+            if (!(nn > 0.0) || !isfinite(nn)) err |= 1;
+            M[i][i] = 1.0 / sqrt(nn);
+        }
+    }
+    for (int j = 0; j < MAXK; ++j)
+        for (int i = 0; i < MAXK; ++i)
+            if (!isfinite(M[j][i])) err |= 1;
+    if (!err) {
+        for (int j = 0; j < MAXK; ++j)
+            for (int i = 0; i < MAXK; ++i) L.coef[j][i] = M[j][i];
+    }
+    L.error |= err;
+    L.step += 1;
+}
+
+// Device-side check of 1 + dtau min(V)/2 > 0 and finiteness (for device-provided V).
+template <typename R>
+__global__ void __launch_bounds__(NT) k_check_potential(const LatDev *lp) {
+    const LatDev &L = *lp;
+    const size_t n3 = (size_t)L.n * L.n * L.n;
+    const R *v = (const R *)L.v;
+    int bad = 0;
+    for (size_t s = (size_t)blockIdx.x * NT + threadIdx.x; s < n3; s += (size_t)gridDim.x * NT) {
+        const double x = (double)v[s];
+        if (!isfinite(x)) bad |= 1;
+        else if (1.0 + L.h * x <= 0.0) bad |= 4;
+    }
+    if (bad) atomicOr((int *)&lp->error, bad);
+}
+
+hipError_t launch_finalize(const JobRef *lats, int nlats, int mode, hipStream_t s) {
+    if (nlats <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize, dim3(nlats), dim3(NT), 0, s, lats, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_potential(const LatDev *lat, int prec, hipStream_t s) {
+    if (prec == ITSE_FP32)
+        hipLaunchKernelGGL(k_check_potential<float>, dim3(256), dim3(NT), 0, s, lat);
+    else
+        hipLaunchKernelGGL(k_check_potential<double>, dim3(256), dim3(NT), 0, s, lat);
+    return hipGetLastError();
+}
+
+}  // namespace itse
+
+// ------------------------------------------------------------------------------------
+// Per-precision dispatch helpers
+// ------------------------------------------------------------------------------------
+namespace itse {
+
+static size_t real_bytes(int prec) { return prec == ITSE_FP32 ? 4 : 8; }
+
+bool prec_supported(int n, int prec) {
+    return prec == ITSE_FP32 ? Launch<float>::supported(n) : Launch<double>::supported(n);
+}
+
+Sched prec_schedule(int n, int prec, int variant) {
+    return prec == ITSE_FP32 ? Launch<float>::schedule(n, variant) : Launch<double>::schedule(n, variant);
+}
+
+// Host-side kinetic tables and stability bound (FP64).
+static void kinetic_axis_table(const itse_desc &d, std::vector<double> &tab) {
+    const int n = d.n;
+    tab.resize(n);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        const int m = (2 * i <= n) ? i : i - n;
+        const double k = 2.0 * pi * (double)m / (double)n;
+        const double s = std::sin(0.5 * k);
+        switch (d.kin) {
+        case ITSE_KIN_NR_CONT: tab[i] = k * k / (2.0 * d.a * d.a * d.mass); break;
+        case ITSE_KIN_NR_LAT: tab[i] = 4.0 * s * s / (2.0 * d.a * d.a * d.mass); break;
+        case ITSE_KIN_REL_LAT: tab[i] = 4.0 * s * s / (d.a * d.a); break;
+        default: tab[i] = k * k / (d.a * d.a); break;
+        }
+    }
+}
+
+double max_symbol(const itse_desc &d) {
+    std::vector<double> tab;
+    kinetic_axis_table(d, tab);
+    const double mx = *std::max_element(tab.begin(), tab.end());
+    const double s = 3.0 * mx;
+    if (d.kin == ITSE_KIN_NR_CONT || d.kin == ITSE_KIN_NR_LAT) return s;
+    const double e = std::sqrt(s + d.mass * d.mass);
+    return d.subtract_rest_mass ? s / (e + d.mass) : e;
+}
+
+// ------------------------------------------------------------------------------------
+// Twiddle tables, shared per (device, n, precision)
+// ------------------------------------------------------------------------------------
+static std::mutex g_tw_mu;
+static std::map<std::tuple<int, int, int>, void *> g_tw;
+
+static itse_status twiddles(int n, int prec, void **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_tw_mu);
+    auto key = std::make_tuple(dev, n, prec);
+    auto it = g_tw.find(key);
+    if (it != g_tw.end()) {
+        *out = it->second;
+        return ITSE_OK;
+    }
+    const double pi = 3.14159265358979323846;
+    std::vector<double> d(2 * n);
+    for (int e = 0; e < n; ++e) {
+        const double ang = -2.0 * pi * (double)e / (double)n;
+        d[2 * e] = std::cos(ang);
+        d[2 * e + 1] = std::sin(ang);
+    }
+    void *p = nullptr;
+    HIPCHK(hipMalloc(&p, 2 * n * real_bytes(prec)));
+    if (prec == ITSE_FP32) {
+        std::vector<float> f(2 * n);
+        for (int e = 0; e < 2 * n; ++e) f[e] = (float)d[e];
+        HIPCHK(hipMemcpy(p, f.data(), f.size() * 4, hipMemcpyHostToDevice));
+    } else {
+        HIPCHK(hipMemcpy(p, d.data(), d.size() * 8, hipMemcpyHostToDevice));
+    }
+    g_tw[key] = p;
+    *out = p;
+    return ITSE_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// Kernel sequences
+// ------------------------------------------------------------------------------------
+template <typename R>
+static hipError_t seq_forward_kin(const Group &g, int inv_mode, hipStream_t s) {
+    hipError_t e;
+    if ((e = Launch<R>::rows_fwd(g.n, g.variant, g.jobs, g.njobs, s)) != hipSuccess) return e;
+    if ((e = Launch<R>::cols(g.n, g.variant, COL_FWD, 1, 0, g.jobs, g.njobs, s)) != hipSuccess) return e;
+    if ((e = Launch<R>::cols(g.n, g.variant, COL_KIN, 0, 1, g.jobs, g.njobs, s)) != hipSuccess) return e;
+    if ((e = Launch<R>::cols(g.n, g.variant, COL_INV, 1, 0, g.jobs, g.njobs, s)) != hipSuccess) return e;
+    return Launch<R>::rows_inv(g.n, g.variant, inv_mode, g.jobs, g.njobs, s);
+}
+
+template <typename R>
+static hipError_t seq_step(const Group &g, hipStream_t s) {
+    hipError_t e;
+    if ((e = seq_forward_kin<R>(g, INV_UPDATE, s)) != hipSuccess) return e;
+    if ((e = Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, s)) != hipSuccess) return e;
+    if ((e = Launch<R>::gram(g.n, g.lats, g.nlats, 0, s)) != hipSuccess) return e;
+    return launch_finalize(g.lats, g.nlats, FIN_STEP, s);
+}
+
+hipError_t enqueue_step(const Group &g, hipStream_t s) {
+    return g.prec == ITSE_FP32 ? seq_step<float>(g, s) : seq_step<double>(g, s);
+}
+
+hipError_t enqueue_eval(const Group &g, hipStream_t s) {
+    hipError_t e = g.prec == ITSE_FP32 ? seq_forward_kin<float>(g, INV_EVAL, s)
+                                       : seq_forward_kin<double>(g, INV_EVAL, s);
+    if (e != hipSuccess) return e;
+    return launch_finalize(g.lats, g.nlats, FIN_EVAL, s);
+}
+
+}  // namespace itse
+
+// ------------------------------------------------------------------------------------
+// Lattice object
+// ------------------------------------------------------------------------------------
+itse_lattice::~itse_lattice() {}
+
+namespace itse {
+
+void *lat_alloc(itse_lattice *L, size_t bytes) {
+    void *p = nullptr;
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (L->alloc) {
+        p = L->alloc(bytes, L->alloc_user);
+    } else {
+        if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    }
+    if (p) L->allocations.push_back(p);
+    return p;
+}
+
+void lat_free_all(itse_lattice *L) {
+    for (void *p : L->allocations) {
+        if (L->freefn) L->freefn(p, L->alloc_user);
+        else if (!L->alloc) (void)hipFree(p);
+    }
+    L->allocations.clear();
+}
+
+itse_status upload_latdev(itse_lattice *L) {
+    HIPCHK(hipMemcpyAsync(L->dev, &L->host, sizeof(LatDev), hipMemcpyHostToDevice, L->stream));
+    return ITSE_OK;
+}
+
+// Write only the option fields (ortho_every .. paxes) to the device copy.
+itse_status upload_opts(itse_lattice *L) {
+    const size_t off = offsetof(LatDev, ortho_every);
+    const size_t len = offsetof(LatDev, coef) - off;
+    HIPCHK(hipMemcpyAsync((char *)L->dev + off, (char *)&L->host + off, len, hipMemcpyHostToDevice, L->stream));
+    return ITSE_OK;
+}
+
+itse_status upload_field(itse_lattice *L, size_t off, size_t len) {
+    HIPCHK(hipMemcpyAsync((char *)L->dev + off, (char *)&L->host + off, len, hipMemcpyHostToDevice, L->stream));
+    return ITSE_OK;
+}
+
+itse_status set_identity_coef(itse_lattice *L) {
+    for (int j = 0; j < MAXK; ++j)
+        for (int i = 0; i < MAXK; ++i) L->host.coef[j][i] = (i == j) ? 1.0 : 0.0;
+    return upload_field(L, offsetof(LatDev, coef), sizeof(L->host.coef));
+}
+
+itse_status check_device_error(itse_lattice *L) {
+    int err = 0;
+    HIPCHK(hipMemcpyAsync(&err, (char *)L->dev + offsetof(LatDev, error), sizeof(int), hipMemcpyDeviceToHost,
+                          L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    if (err) {
+        int zero = 0;
+        HIPCHK(hipMemcpy((char *)L->dev + offsetof(LatDev, error), &zero, sizeof(int), hipMemcpyHostToDevice));
+        if (err & 4) return fail(ITSE_EUNSTABLE, "potential violates 1 + dtau min(V)/2 > 0");
+        if (err & 2) return fail(ITSE_ENONFINITE, "Gram matrix not positive definite (states linearly dependent)");
+        return fail(ITSE_ENONFINITE, "non-finite value in a reduction (NaN/Inf in state or potential)");
+    }
+    return ITSE_OK;
+}
+
+Group single_group(itse_lattice *L) {
+    Group g;
+    g.n = L->d.n;
+    g.prec = L->d.precision;
+    g.variant = L->variant;
+    g.jobs = L->jobs_dev;
+    g.njobs = L->d.nstates;
+    g.lats = L->lat_dev;
+    g.nlats = 1;
+    return g;
+}
+
+Group state_group(itse_lattice *L, int i) {
+    Group g = single_group(L);
+    g.jobs = L->jobs_dev + i;
+    g.njobs = 1;
+    return g;
+}
+
+// Replace the lazy representation by materialised states: phi_i = sum_j coef[j][i] u_j,
+// copy phi -> u, coef = identity.
+itse_status materialise(itse_lattice *L) {
+    const int K = L->d.nstates;
+    const size_t bytes = (size_t)L->d.n * L->d.n * L->d.n * real_bytes(L->d.precision);
+    hipError_t e = L->d.precision == ITSE_FP32
+                       ? Launch<float>::combine(L->d.n, L->jobs_dev, K, L->phi_ptrs_dev, L->stream)
+                       : Launch<double>::combine(L->d.n, L->jobs_dev, K, L->phi_ptrs_dev, L->stream);
+    if (e != hipSuccess) return fail(ITSE_EDEVICE, "combine launch: %s", hipGetErrorString(e));
+    for (int i = 0; i < K; ++i)
+        HIPCHK(hipMemcpyAsync(L->host.u[i], L->host.phi[i], bytes, hipMemcpyDeviceToDevice, L->stream));
+    return set_identity_coef(L);
+}
+
+}  // namespace itse
+
+extern "C" size_t itse_footprint_bytes(const itse_desc *d) {
+    if (!d || d->n < 1) return 0;
+    const size_t w = real_bytes(d->precision);
+    const size_t n = (size_t)d->n, n3 = n * n * n;
+    const size_t K = (size_t)std::max(1, std::min(d->nstates, MAXK));
+    const size_t spec = n * n * (n / 2 + 1) * 2 * w;
+    Sched s = prec_supported(d->n, d->precision) ? prec_schedule(d->n, d->precision, 0) : Sched{};
+    const size_t arena = (size_t)MAXK * ((size_t)s.nb_rows * NQR + (size_t)s.nb_cols * NQC + s.nb_proj) * 8 +
+                         (size_t)s.nb_gram * (MAXK * (MAXK + 1) / 2) * 8;
+    const size_t hist = (size_t)HIST_CAP * MAXK * sizeof(ObsDev);
+    return K * (2 * n3 * w + spec) + n3 * w + n3 * w /*temp*/ + arena + hist + sizeof(LatDev) + 4096 + n * 8;
+}
+
+static bool valid_n(int n) {
+    if (n < 8 || n > 512) return false;
+    int m = n;
+    while (m % 2 == 0) m /= 2;
+    while (m % 3 == 0) m /= 3;
+    return m == 1;
+}
+
+extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_alloc_fn alloc, itse_free_fn free_fn,
+                                   void *alloc_user, itse_lattice **out) {
+    if (!d || !out) return fail(ITSE_EINVAL, "null argument");
+    *out = nullptr;
+    if (!valid_n(d->n)) return fail(ITSE_EINVAL, "n = %d: need 8 <= n <= 512 with prime factors 2 and 3", d->n);
+    if (!(d->a > 0) || !(d->mass > 0) || !(d->dtau > 0) || !std::isfinite(d->a) || !std::isfinite(d->mass) ||
+        !std::isfinite(d->dtau))
+        return fail(ITSE_EINVAL, "a, mass and dtau must be finite and > 0");
+    if (d->kin < 1 || d->kin > 4) return fail(ITSE_EINVAL, "kin = %d", d->kin);
+    if (d->precision != ITSE_FP32 && d->precision != ITSE_FP64) return fail(ITSE_EINVAL, "precision");
+    if (d->center != ITSE_CENTER_CELL && d->center != ITSE_CENTER_ORIGIN) return fail(ITSE_EINVAL, "center");
+    if (d->nstates < 1 || d->nstates > MAXK) return fail(ITSE_EINVAL, "nstates = %d (1..%d)", d->nstates, MAXK);
+    if (!prec_supported(d->n, d->precision)) return fail(ITSE_EINVAL, "n = %d not built", d->n);
+    const double tmax = max_symbol(*d);
+    if (d->dtau * tmax > 1.95)
+        return fail(ITSE_EUNSTABLE, "dtau * max T(k) = %.4f > 1.95 (step map would amplify the highest modes)",
+                    d->dtau * tmax);
+
+    itse_lattice *L = new itse_lattice();
+    L->d = *d;
+    L->stream = (hipStream_t)hip_stream;
+    L->alloc = alloc;
+    L->freefn = free_fn;
+    L->alloc_user = alloc_user;
+    L->variant = schedule_variant_for(d->n, d->precision);
+    L->sched = prec_schedule(d->n, d->precision, L->variant);
+    const int n = d->n, K = d->nstates;
+    const size_t w = real_bytes(d->precision);
+    const size_t n3 = (size_t)n * n * n;
+    const size_t spec = (size_t)n * n * (n / 2 + 1) * 2 * w;
+    auto cleanup = [&](itse_status st) {
+        lat_free_all(L);
+        delete L;
+        return st;
+    };
+    LatDev &H = L->host;
+    std::memset(&H, 0, sizeof(H));
+    H.n = n;
+    H.nstates = K;
+    H.kin = d->kin;
+    H.sub = d->subtract_rest_mass ? 1 : 0;
+    H.center = d->center;
+    H.prec = d->precision;
+    H.a = d->a;
+    H.mass = d->mass;
+    H.dtau = d->dtau;
+    H.h = 0.5 * d->dtau;
+    for (int i = 0; i < K; ++i) {
+        H.u[i] = lat_alloc(L, n3 * w);
+        H.phi[i] = lat_alloc(L, n3 * w);
+        H.spec[i] = lat_alloc(L, spec);
+        if (!H.u[i] || !H.phi[i] || !H.spec[i]) return cleanup(fail(ITSE_ENOMEM, "state buffers (%zu bytes)", n3 * w));
+    }
+    H.v = lat_alloc(L, n3 * w);
+    L->tmp = lat_alloc(L, n3 * w);
+    H.nb_rows = L->sched.nb_rows;
+    H.nb_cols = L->sched.nb_cols;
+    H.nb_proj = L->sched.nb_proj;
+    H.nb_gram = L->sched.nb_gram;
+    H.part_rows = (double *)lat_alloc(L, (size_t)MAXK * H.nb_rows * NQR * 8);
+    H.part_cols = (double *)lat_alloc(L, (size_t)MAXK * H.nb_cols * NQC * 8);
+    H.part_proj = (double *)lat_alloc(L, (size_t)MAXK * H.nb_proj * 8);
+    H.part_gram = (double *)lat_alloc(L, (size_t)H.nb_gram * (MAXK * (MAXK + 1) / 2) * 8);
+    H.hist = (ObsDev *)lat_alloc(L, (size_t)HIST_CAP * MAXK * sizeof(ObsDev));
+    double *ktab = (double *)lat_alloc(L, (size_t)n * 8);
+    L->dev = (LatDev *)lat_alloc(L, sizeof(LatDev));
+    L->jobs_dev = (JobRef *)lat_alloc(L, sizeof(JobRef) * MAXK);
+    L->lat_dev = (JobRef *)lat_alloc(L, sizeof(JobRef));
+    L->phi_ptrs_dev = (void **)lat_alloc(L, sizeof(void *) * MAXK);
+    L->tmp_ptrs_dev = (void **)lat_alloc(L, sizeof(void *) * MAXK);
+    if (!H.v || !L->tmp || !H.part_rows || !H.part_cols || !H.part_proj || !H.part_gram || !H.hist || !ktab ||
+        !L->dev || !L->jobs_dev || !L->lat_dev || !L->phi_ptrs_dev || !L->tmp_ptrs_dev)
+        return cleanup(fail(ITSE_ENOMEM, "lattice buffers"));
+    H.ktab = ktab;
+    void *tw = nullptr;
+    itse_status st = twiddles(n, d->precision, &tw);
+    if (st) return cleanup(st);
+    H.tw = tw;
+    H.ortho_every = 1;
+    H.moments = 0;
+    for (int i = 0; i < MAXK; ++i) {
+        H.psign[i] = 0;
+        H.paxes[i] = 7;
+    }
+    for (int j = 0; j < MAXK; ++j)
+        for (int i = 0; i < MAXK; ++i) H.coef[j][i] = (i == j) ? 1.0 : 0.0;
+    H.step = 0;
+    H.error = 0;
+    L->opts.ortho_every = 1;
+    L->opts.moments = 0;
+    for (int i = 0; i < MAXK; ++i) {
+        L->opts.parity[i] = 0;
+        L->opts.axes[i] = 7;
+    }
+
+    std::vector<double> tab;
+    kinetic_axis_table(*d, tab);
+    std::vector<JobRef> jobs(MAXK);
+    std::vector<void *> phis(MAXK, nullptr), tmps(MAXK, nullptr);
+    for (int i = 0; i < MAXK; ++i) {
+        jobs[i].lat = L->dev;
+        jobs[i].state = i;
+        jobs[i].pad_ = 0;
+        phis[i] = H.phi[i];
+        tmps[i] = L->tmp;
+    }
+    JobRef lj{L->dev, 0, 0};
+    auto s = L->stream;
+#define CK(expr)                                                                                  \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return cleanup(fail(ITSE_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_))); \
+    } while (0)
+    CK(hipMemcpyAsync(ktab, tab.data(), n * 8, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(L->jobs_dev, jobs.data(), sizeof(JobRef) * MAXK, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(L->lat_dev, &lj, sizeof(JobRef), hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(L->phi_ptrs_dev, phis.data(), sizeof(void *) * MAXK, hipMemcpyHostToDevice, s));
+    CK(hipMemcpyAsync(L->tmp_ptrs_dev, tmps.data(), sizeof(void *) * MAXK, hipMemcpyHostToDevice, s));
+    for (int i = 0; i < K; ++i) {
+        CK(hipMemsetAsync(H.u[i], 0, n3 * w, s));
+        CK(hipMemsetAsync(H.phi[i], 0, n3 * w, s));
+    }
+    CK(hipMemsetAsync(H.v, 0, n3 * w, s));
+    CK(hipMemsetAsync(H.hist, 0, (size_t)HIST_CAP * MAXK * sizeof(ObsDev), s));
+    CK(hipMemcpyAsync(L->dev, &H, sizeof(LatDev), hipMemcpyHostToDevice, s));
+    CK(hipStreamSynchronize(s));
+#undef CK
+    *out = L;
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_destroy(itse_lattice *L) {
+    if (!L) return ITSE_OK;
+    (void)hipStreamSynchronize(L->stream);
+    if (L->graph1) (void)hipGraphExecDestroy(L->graph1);
+    if (L->graphN) (void)hipGraphExecDestroy(L->graphN);
+    if (L->cap_stream) (void)hipStreamDestroy(L->cap_stream);
+    if (L->shadow) itse_destroy(L->shadow);
+    lat_free_all(L);
+    delete L;
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_set_stream(itse_lattice *L, void *stream) {
+    if (!L) return fail(ITSE_EINVAL, "null lattice");
+    HIPCHK(hipStreamSynchronize(L->stream));
+    L->stream = (hipStream_t)stream;
+    return ITSE_OK;
+}
+
+namespace itse {
+// Copy N^3 values of dtype `dtype` from host/device into a lattice buffer of the lattice precision.
+static itse_status copy_in(itse_lattice *L, const void *src, int dtype, int on_device, void *dst) {
+    const size_t n3 = (size_t)L->d.n * L->d.n * L->d.n;
+    const int prec = L->d.precision;
+    const size_t sw = dtype == ITSE_DTYPE_F32 ? 4 : 8;
+    const bool same = (dtype == ITSE_DTYPE_F32) == (prec == ITSE_FP32);
+    if (same) {
+        HIPCHK(hipMemcpyAsync(dst, src, n3 * sw, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                              L->stream));
+        if (!on_device) HIPCHK(hipStreamSynchronize(L->stream));
+        return ITSE_OK;
+    }
+    const void *dsrc = src;
+    void *staging = nullptr;
+    if (!on_device) {
+        // stage in the phi buffer of the last state is unsafe; use a dedicated buffer
+        staging = L->stage_buf(n3 * sw);
+        if (!staging) return fail(ITSE_ENOMEM, "staging buffer");
+        HIPCHK(hipMemcpyAsync(staging, src, n3 * sw, hipMemcpyHostToDevice, L->stream));
+        dsrc = staging;
+    }
+    hipError_t e = prec == ITSE_FP32 ? Launch<float>::convert_in(dsrc, dtype, dst, n3, L->stream)
+                                     : Launch<double>::convert_in(dsrc, dtype, dst, n3, L->stream);
+    if (e != hipSuccess) return fail(ITSE_EDEVICE, "convert: %s", hipGetErrorString(e));
+    if (!on_device) HIPCHK(hipStreamSynchronize(L->stream));
+    return ITSE_OK;
+}
+}  // namespace itse
+
+void *itse_lattice::stage_buf(size_t bytes) {
+    if (staging && staging_bytes >= bytes) return staging;
+    staging = itse::lat_alloc(this, bytes);
+    staging_bytes = staging ? bytes : 0;
+    return staging;
+}
+
+extern "C" itse_status itse_set_potential(itse_lattice *L, const void *v, int dtype, int on_device) {
+    if (!L || !v) return fail(ITSE_EINVAL, "null argument");
+    if (dtype != ITSE_DTYPE_F32 && dtype != ITSE_DTYPE_F64) return fail(ITSE_EINVAL, "dtype");
+    const size_t n3 = (size_t)L->d.n * L->d.n * L->d.n;
+    if (!on_device) {
+        double vmin = 0.0;
+        for (size_t s = 0; s < n3; ++s) {
+            const double x = dtype == ITSE_DTYPE_F32 ? (double)((const float *)v)[s] : ((const double *)v)[s];
+            if (!std::isfinite(x)) return fail(ITSE_ENONFINITE, "potential has a non-finite value at site %zu", s);
+            if (s == 0 || x < vmin) vmin = x;
+        }
+        if (1.0 + 0.5 * L->d.dtau * vmin <= 0.0)
+            return fail(ITSE_EUNSTABLE, "1 + dtau min(V)/2 = %.4g <= 0", 1.0 + 0.5 * L->d.dtau * vmin);
+    }
+    itse_status st = copy_in(L, v, dtype, on_device, L->host.v);
+    if (st) return st;
+    if (on_device) {
+        hipError_t e = launch_check_potential(L->dev, L->d.precision, L->stream);
+        if (e != hipSuccess) return fail(ITSE_EDEVICE, "check_potential: %s", hipGetErrorString(e));
+    }
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_set_state(itse_lattice *L, int i, const void *psi, int dtype, int on_device) {
+    if (!L || !psi) return fail(ITSE_EINVAL, "null argument");
+    if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
+    if (dtype != ITSE_DTYPE_F32 && dtype != ITSE_DTYPE_F64) return fail(ITSE_EINVAL, "dtype");
+    itse_status st = materialise(L);
+    if (st) return st;
+    return copy_in(L, psi, dtype, on_device, L->host.u[i]);
+}
+
+extern "C" itse_status itse_get_state(itse_lattice *L, int i, void *out, int dtype, int on_device) {
+    if (!L || !out) return fail(ITSE_EINVAL, "null argument");
+    if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
+    if (dtype != ITSE_DTYPE_F32 && dtype != ITSE_DTYPE_F64) return fail(ITSE_EINVAL, "dtype");
+    const size_t n3 = (size_t)L->d.n * L->d.n * L->d.n;
+    const int prec = L->d.precision;
+    hipError_t e = prec == ITSE_FP32 ? Launch<float>::combine(L->d.n, L->jobs_dev + i, 1, L->tmp_ptrs_dev, L->stream)
+                                     : Launch<double>::combine(L->d.n, L->jobs_dev + i, 1, L->tmp_ptrs_dev, L->stream);
+    if (e != hipSuccess) return fail(ITSE_EDEVICE, "combine: %s", hipGetErrorString(e));
+    const size_t dw = dtype == ITSE_DTYPE_F32 ? 4 : 8;
+    const bool same = (dtype == ITSE_DTYPE_F32) == (prec == ITSE_FP32);
+    const void *src = L->tmp;
+    if (!same) {
+        void *stg = L->stage_buf(n3 * dw);
+        if (!stg) return fail(ITSE_ENOMEM, "staging buffer");
+        e = prec == ITSE_FP32 ? Launch<float>::convert_out(L->tmp, stg, dtype, n3, L->stream)
+                              : Launch<double>::convert_out(L->tmp, stg, dtype, n3, L->stream);
+        if (e != hipSuccess) return fail(ITSE_EDEVICE, "convert: %s", hipGetErrorString(e));
+        src = stg;
+    }
+    HIPCHK(hipMemcpyAsync(out, src, n3 * dw, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, L->stream));
+    if (!on_device) HIPCHK(hipStreamSynchronize(L->stream));
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_set_step_opts(itse_lattice *L, const itse_step_opts *o) {
+    if (!L || !o) return fail(ITSE_EINVAL, "null argument");
+    if (o->ortho_every < 0) return fail(ITSE_EINVAL, "ortho_every < 0");
+    for (int i = 0; i < MAXK; ++i) {
+        if (o->parity[i] < -1 || o->parity[i] > 1) return fail(ITSE_EINVAL, "parity[%d] = %d", i, o->parity[i]);
+        if (o->parity[i] != 0 && (o->axes[i] < 1 || o->axes[i] > 7))
+            return fail(ITSE_EINVAL, "axes[%d] = %d", i, o->axes[i]);
+    }
+    L->opts = *o;
+    L->host.ortho_every = o->ortho_every;
+    L->host.moments = o->moments ? 1 : 0;
+    for (int i = 0; i < MAXK; ++i) {
+        L->host.psign[i] = i < L->d.nstates ? o->parity[i] : 0;
+        L->host.paxes[i] = o->parity[i] ? o->axes[i] : 7;
+    }
+    return upload_opts(L);
+}
+
+namespace itse {
+static bool graphs_enabled() {
+    const char *e = getenv("ITSE_GRAPHS");
+    return !(e && e[0] == '0');
+}
+
+// Capture `nsteps` step sequences of group set `groups` into an executable graph.
+itse_status capture_steps(hipStream_t cap, const std::vector<Group> &groups, int nsteps,
+                          std::vector<hipStream_t> &branch, hipGraphExec_t *out) {
+    HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    hipError_t err = hipSuccess;
+    std::vector<hipEvent_t> evs;
+    if (groups.size() == 1) {
+        for (int s = 0; s < nsteps && err == hipSuccess; ++s) err = enqueue_step(groups[0], cap);
+    } else {
+        // fork: each group on its own branch stream, joined at the end
+        hipEvent_t fork;
+        (void)hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        evs.push_back(fork);
+        (void)hipEventRecord(fork, cap);
+        for (size_t g = 0; g < groups.size() && err == hipSuccess; ++g) {
+            hipStream_t bs = branch[g % branch.size()];
+            (void)hipStreamWaitEvent(bs, fork, 0);
+            for (int s = 0; s < nsteps && err == hipSuccess; ++s) err = enqueue_step(groups[g], bs);
+            hipEvent_t join;
+            (void)hipEventCreateWithFlags(&join, hipEventDisableTiming);
+            evs.push_back(join);
+            (void)hipEventRecord(join, bs);
+            (void)hipStreamWaitEvent(cap, join, 0);
+        }
+    }
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cap, &graph);
+    for (auto ev : evs) (void)hipEventDestroy(ev);
+    if (err != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(ITSE_EDEVICE, "launch during capture: %s", hipGetErrorString(err));
+    }
+    if (e2 != hipSuccess) return fail(ITSE_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e2));
+    hipError_t e3 = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) return fail(ITSE_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e3));
+    return ITSE_OK;
+}
+}  // namespace itse
+
+extern "C" itse_status itse_step(itse_lattice *L, int nsteps, const itse_step_opts *opts) {
+    if (!L) return fail(ITSE_EINVAL, "null lattice");
+    if (nsteps < 0) return fail(ITSE_EINVAL, "nsteps < 0");
+    if (opts) {
+        itse_status st = itse_set_step_opts(L, opts);
+        if (st) return st;
+    }
+    if (nsteps == 0) return ITSE_OK;
+    Group g = single_group(L);
+    if (!graphs_enabled()) {
+        for (int s = 0; s < nsteps; ++s) {
+            hipError_t e = enqueue_step(g, L->stream);
+            if (e != hipSuccess) return fail(ITSE_EDEVICE, "step launch: %s", hipGetErrorString(e));
+        }
+        L->steps_host += nsteps;
+        return ITSE_OK;
+    }
+    if (!L->cap_stream) HIPCHK(hipStreamCreateWithFlags(&L->cap_stream, hipStreamNonBlocking));
+    std::vector<hipStream_t> br{L->cap_stream};
+    const int chunk = ITSE_GRAPH_CHUNK;
+    if (nsteps >= chunk && !L->graphN) {
+        itse_status st = capture_steps(L->cap_stream, {g}, chunk, br, &L->graphN);
+        if (st) return st;
+    }
+    if (!L->graph1) {
+        itse_status st = capture_steps(L->cap_stream, {g}, 1, br, &L->graph1);
+        if (st) return st;
+    }
+    int left = nsteps;
+    while (left >= chunk) {
+        HIPCHK(hipGraphLaunch(L->graphN, L->stream));
+        left -= chunk;
+    }
+    while (left > 0) {
+        HIPCHK(hipGraphLaunch(L->graph1, L->stream));
+        --left;
+    }
+    L->steps_host += nsteps;
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_evaluate(itse_lattice *L, int moments) {
+    if (!L) return fail(ITSE_EINVAL, "null lattice");
+    const int saved = L->host.moments;
+    L->host.moments = moments ? 1 : 0;
+    itse_status st = upload_field(L, offsetof(LatDev, moments), sizeof(int));
+    if (st) return st;
+    hipError_t e = enqueue_eval(single_group(L), L->stream);
+    if (e != hipSuccess) return fail(ITSE_EDEVICE, "evaluate launch: %s", hipGetErrorString(e));
+    L->host.moments = saved;
+    return upload_field(L, offsetof(LatDev, moments), sizeof(int));
+}
+
+extern "C" itse_status itse_observe(itse_lattice *L, int i, itse_obs *out) {
+    if (!L || !out) return fail(ITSE_EINVAL, "null argument");
+    if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
+    ObsDev o;
+    HIPCHK(hipMemcpyAsync(&o, (char *)L->dev + offsetof(LatDev, obs) + i * sizeof(ObsDev), sizeof(ObsDev),
+                          hipMemcpyDeviceToHost, L->stream));
+    itse_status st = check_device_error(L);
+    static_assert(sizeof(ObsDev) == sizeof(itse_obs), "observable layout");
+    std::memcpy(out, &o, sizeof(o));
+    return st;
+}
+
+extern "C" itse_status itse_history(itse_lattice *L, int count, itse_obs *out) {
+    if (!L || (!out && count > 0)) return fail(ITSE_EINVAL, "null argument");
+    if (count < 0 || count > HIST_CAP || count > L->steps_host)
+        return fail(ITSE_EINVAL, "count %d (steps taken %lld, capacity %d)", count, L->steps_host, HIST_CAP);
+    const int K = L->d.nstates;
+    std::vector<ObsDev> all((size_t)HIST_CAP * MAXK);
+    HIPCHK(hipMemcpyAsync(all.data(), L->host.hist, all.size() * sizeof(ObsDev), hipMemcpyDeviceToHost, L->stream));
+    itse_status st = check_device_error(L);
+    const long long last = L->steps_host;  // steps 0..last-1 recorded
+    for (int c = 0; c < count; ++c) {
+        const long long step = last - count + c;
+        const size_t slot = (size_t)(step % HIST_CAP);
+        for (int i = 0; i < K; ++i) std::memcpy(&out[(size_t)c * K + i], &all[slot * MAXK + i], sizeof(itse_obs));
+    }
+    return st;
+}
+
+extern "C" long long itse_step_count(const itse_lattice *L) { return L ? L->steps_host : -1; }
+
+extern "C" itse_status itse_sync(itse_lattice *L) {
+    if (!L) return fail(ITSE_EINVAL, "null lattice");
+    return check_device_error(L);
+}
+
+namespace itse {
+// Sum per-block partials on the host in the same fixed order the device uses.
+static double host_fixed_sum(const std::vector<double> &p, int count, int stride, int off) {
+    std::vector<double> red(NT, 0.0);
+    for (int t = 0; t < NT; ++t)
+        for (int b = t; b < count; b += NT) red[t] += p[(size_t)b * stride + off];
+    for (int s = NT / 2; s > 0; s >>= 1)
+        for (int t = 0; t < s; ++t) red[t] += red[t + s];
+    return red[0];
+}
+
+static itse_status gram_host(itse_lattice *L, double G[MAXK][MAXK]) {
+    constexpr int NG = MAXK * (MAXK + 1) / 2;
+    hipError_t e = L->d.precision == ITSE_FP32 ? Launch<float>::gram(L->d.n, L->lat_dev, 1, 1, L->stream)
+                                               : Launch<double>::gram(L->d.n, L->lat_dev, 1, 1, L->stream);
+    if (e != hipSuccess) return fail(ITSE_EDEVICE, "gram: %s", hipGetErrorString(e));
+    std::vector<double> part((size_t)L->host.nb_gram * NG);
+    HIPCHK(hipMemcpyAsync(part.data(), L->host.part_gram, part.size() * 8, hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    const int K = L->d.nstates;
+    for (int l = 0; l < K; ++l)
+        for (int j = 0; j <= l; ++j) {
+            const double s = host_fixed_sum(part, L->host.nb_gram, NG, l * (l + 1) / 2 + j);
+            G[j][l] = G[l][j] = s;
+        }
+    return ITSE_OK;
+}
+}  // namespace itse
+
+extern "C" itse_status itse_orthogonalise(itse_lattice *L, int i) {
+    if (!L) return fail(ITSE_EINVAL, "null lattice");
+    if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
+    itse_status st = materialise(L);
+    if (st) return st;
+    double G[MAXK][MAXK] = {};
+    if (L->d.nstates == 1) {
+        // one state: only the norm
+        G[0][0] = 0.0;
+    }
+    // the Gram kernel needs nstates >= 2; for one state compute the norm via a forced projection-free sum
+    if (L->d.nstates >= 2) {
+        st = gram_host(L, G);
+        if (st) return st;
+    } else {
+        st = norm_host(L, 0, &G[0][0]);
+        if (st) return st;
+    }
+    // Cholesky of the leading (i+1)x(i+1) block; column i of R^{-1}
+    double Rm[MAXK][MAXK] = {};
+    for (int j = 0; j <= i; ++j)
+        for (int c = j; c <= i; ++c) {
+            double s = G[j][c];
+            for (int l = 0; l < j; ++l) s -= Rm[l][j] * Rm[l][c];
+            if (c == j) {
+                if (!(s > 0.0)) return fail(ITSE_ENONFINITE, "state %d lies in the span of the lower states", i);
+                Rm[j][j] = std::sqrt(s);
+            } else {
+                Rm[j][c] = s / Rm[j][j];
+            }
+        }
+    double M[MAXK] = {};
+    M[i] = 1.0 / Rm[i][i];
+    for (int j = i - 1; j >= 0; --j) {
+        double s = 0.0;
+        for (int l = j + 1; l <= i; ++l) s += Rm[j][l] * M[l];
+        M[j] = -s / Rm[j][j];
+    }
+    for (int j = 0; j < MAXK; ++j) L->host.coef[j][i] = j <= i ? M[j] : 0.0;
+    return upload_field(L, offsetof(LatDev, coef), sizeof(L->host.coef));
+}
+
+namespace itse {
+itse_status norm_host(itse_lattice *L, int i, double *out) {
+    // sum of squares of u_i via the projection kernel's partials with sign +1 on axes 0
+    // is not available; use the combine-free path: copy to host and sum in FP64.
+    const size_t n3 = (size_t)L->d.n * L->d.n * L->d.n;
+    std::vector<double> h(n3);
+    itse_status st = itse_get_state(L, i, h.data(), ITSE_DTYPE_F64, 0);
+    if (st) return st;
+    double acc = 0.0;
+    for (size_t s = 0; s < n3; ++s) acc += h[s] * h[s];
+    *out = acc;
+    return ITSE_OK;
+}
+}  // namespace itse
+
+extern "C" itse_status itse_project_parity(itse_lattice *L, int i, int sign, int axes, double *weight) {
+    if (!L) return fail(ITSE_EINVAL, "null lattice");
+    if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
+    if (sign != 1 && sign != -1) return fail(ITSE_EINVAL, "sign must be +1 or -1");
+    if (axes < 1 || axes > 7) return fail(ITSE_EINVAL, "axes must be in 1..7");
+    itse_status st = materialise(L);
+    if (st) return st;
+    double before = 0.0;
+    st = norm_host(L, i, &before);
+    if (st) return st;
+    hipError_t e = L->d.precision == ITSE_FP32
+                       ? Launch<float>::project(L->d.n, L->jobs_dev + i, 1, sign, axes, L->stream)
+                       : Launch<double>::project(L->d.n, L->jobs_dev + i, 1, sign, axes, L->stream);
+    if (e != hipSuccess) return fail(ITSE_EDEVICE, "project: %s", hipGetErrorString(e));
+    std::vector<double> part(L->host.nb_proj);
+    HIPCHK(hipMemcpyAsync(part.data(), L->host.part_proj + (size_t)i * L->host.nb_proj, part.size() * 8,
+                          hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    const double after = host_fixed_sum(part, L->host.nb_proj, 1, 0);
+    if (weight) *weight = before > 0 ? after / before : 0.0;
+    if (!(after > 0.0)) return fail(ITSE_ENONFINITE, "projection of state %d vanishes", i);
+    for (int j = 0; j < MAXK; ++j) L->host.coef[j][i] = (j == i) ? 1.0 / std::sqrt(after) : 0.0;
+    return upload_field(L, offsetof(LatDev, coef), sizeof(L->host.coef));
+}
+
+extern "C" itse_status itse_apply_kinetic(itse_lattice *L, int i, void *out) {
+    if (!L || !out) return fail(ITSE_EINVAL, "null argument");
+    if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
+    L->host.kout = out;
+    itse_status st = upload_field(L, offsetof(LatDev, kout), sizeof(void *));
+    if (st) return st;
+    Group g = state_group(L, i);
+    hipError_t e = L->d.precision == ITSE_FP32 ? seq_forward_kin<float>(g, INV_KOUT, L->stream)
+                                               : seq_forward_kin<double>(g, INV_KOUT, L->stream);
+    if (e != hipSuccess) return fail(ITSE_EDEVICE, "kinetic launch: %s", hipGetErrorString(e));
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_spectrum(itse_lattice *L, int i, void *out) {
+    if (!L || !out) return fail(ITSE_EINVAL, "null argument");
+    if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
+    Group g = state_group(L, i);
+    hipError_t e;
+    if (L->d.precision == ITSE_FP32) {
+        e = Launch<float>::rows_fwd(g.n, g.variant, g.jobs, 1, L->stream);
+        if (e == hipSuccess) e = Launch<float>::cols(g.n, g.variant, COL_FWD, 1, 0, g.jobs, 1, L->stream);
+        if (e == hipSuccess) e = Launch<float>::cols(g.n, g.variant, COL_FWD, 0, 0, g.jobs, 1, L->stream);
+    } else {
+        e = Launch<double>::rows_fwd(g.n, g.variant, g.jobs, 1, L->stream);
+        if (e == hipSuccess) e = Launch<double>::cols(g.n, g.variant, COL_FWD, 1, 0, g.jobs, 1, L->stream);
+        if (e == hipSuccess) e = Launch<double>::cols(g.n, g.variant, COL_FWD, 0, 0, g.jobs, 1, L->stream);
+    }
+    if (e != hipSuccess) return fail(ITSE_EDEVICE, "spectrum launch: %s", hipGetErrorString(e));
+    const size_t n = L->d.n;
+    const size_t bytes = n * n * (n / 2 + 1) * 2 * real_bytes(L->d.precision);
+    HIPCHK(hipMemcpyAsync(out, L->host.spec[i], bytes, hipMemcpyDeviceToDevice, L->stream));
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_polish(itse_lattice *L, int i, itse_obs *out) {
+    if (!L || !out) return fail(ITSE_EINVAL, "null argument");
+    if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
+    if (L->d.precision == ITSE_FP64) {
+        itse_status st = itse_evaluate(L, 1);
+        if (st) return st;
+        return itse_observe(L, i, out);
+    }
+    if (!L->shadow) {
+        itse_desc d = L->d;
+        d.precision = ITSE_FP64;
+        d.nstates = 1;
+        itse_status st = itse_create(&d, L->stream, L->alloc, L->freefn, L->alloc_user, &L->shadow);
+        if (st) return st;
+    }
+    itse_lattice *S = L->shadow;
+    itse_set_stream(S, L->stream);
+    // potential and state: FP32 values widened exactly to FP64
+    itse_status st = itse_set_potential(S, L->host.v, ITSE_DTYPE_F32, 1);
+    if (st) return st;
+    hipError_t e = Launch<float>::combine(L->d.n, L->jobs_dev + i, 1, L->tmp_ptrs_dev, L->stream);
+    if (e != hipSuccess) return fail(ITSE_EDEVICE, "combine: %s", hipGetErrorString(e));
+    st = itse_set_state(S, 0, L->tmp, ITSE_DTYPE_F32, 1);
+    if (st) return st;
+    st = itse_evaluate(S, 1);
+    if (st) return st;
+    return itse_observe(S, 0, out);
+}

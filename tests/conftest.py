@@ -18,3 +18,21 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    """Name each GPU case before it runs (flushed), so a failing run identifies it."""
+    if request.node.get_closest_marker("gpu") is not None:
+        print(f"\n[gpu-case] {request.node.nodeid}", flush=True)
+    yield
+
+
+@pytest.fixture(scope="session")
+def itse():
+    import paper_2006_16935_amd as pkg
+    pkg.load()
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return pkg

@@ -1,0 +1,270 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances:
+* FP64 lattices: 1e-12 relative (max-abs / max) for single transforms and
+  kinetic applications; 1e-10 relative for energies and states along whole
+  trajectories.
+* FP32 lattices (FP32 storage and transforms, FP64 sums): one transform has a
+  relative error ~ eps32 * log2(N) (6e-8 * 8 at N = 256); the bound used is
+  2e-5 of max|K psi| element-wise and 1e-5 relative on energies of a step.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+KINDS = [(1, True), (2, True), (3, True), (3, False), (4, True)]
+
+
+def _lat(itse, n, kin=3, sub=True, prec="fp64", center="origin", nstates=1, a=0.1, mass=1.3,
+         dtau=None):
+    if dtau is None:
+        dtau = a * a * mass / 8 if kin in (1, 2) else a / 4
+    return itse.Lattice(n, a, mass, dtau, kin=kin, subtract_rest_mass=sub, precision=prec,
+                        center=center, nstates=nstates)
+
+
+def _olat(orc, lat):
+    d = lat.desc
+    return orc.lattice(d.n, d.a, d.mass, d.dtau, d.kin, bool(d.subtract_rest_mass),
+                       "cell" if d.center == 0 else "origin")
+
+
+def _rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+@pytest.mark.parametrize("n", [8, 12, 16, 24, 32, 48, 64])
+def test_spectrum_fp64(itse, orc, n):
+    lat = _lat(itse, n)
+    psi = synth.random_state(n, 100 + n)
+    lat.set_state(0, psi)
+    spec = lat.spectrum(0).cpu().numpy()
+    got = spec[..., 0] + 1j * spec[..., 1]
+    ref = orc.fft3d(psi, -1)[:, :, : n // 2 + 1]
+    assert _rel(got, ref) < 1e-12
+    lat.close()
+
+
+@pytest.mark.parametrize("n", [8, 12, 24, 48, 96])
+@pytest.mark.parametrize("kin,sub", KINDS)
+def test_apply_kinetic_fp64(itse, orc, n, kin, sub):
+    lat = _lat(itse, n, kin, sub)
+    psi = synth.random_state(n, 7 * n + kin)
+    lat.set_state(0, psi)
+    got = lat.apply_kinetic(0).cpu().numpy()
+    ref = orc.apply_kinetic(_olat(orc, lat), psi)
+    assert _rel(got, ref) < 1e-12
+    lat.close()
+
+
+@pytest.mark.parametrize("n", [16, 32, 64, 128])
+@pytest.mark.parametrize("kin,sub", [(1, True), (3, True)])
+def test_apply_kinetic_fp32(itse, orc, n, kin, sub):
+    lat = _lat(itse, n, kin, sub, prec="fp32")
+    psi = synth.random_state(n, 11 * n, dtype=np.float32)
+    lat.set_state(0, psi)
+    got = lat.apply_kinetic(0).cpu().numpy().astype(np.float64)
+    ref = orc.apply_kinetic(_olat(orc, lat), psi.astype(np.float64))
+    assert _rel(got, ref) < 2e-5
+
+
+def test_plain_config_trajectory(itse, orc):
+    """32^3 H_K^(1) oscillator, dtau = a^2/8, state from seed 0, 2000 steps in FP64:
+    every step's energy and the final state match the oracle to 1e-10."""
+    p = synth.config_plain_fp64()
+    lat = itse.Lattice(p.n, p.a, p.mass, p.dtau, kin=p.kin, precision="fp64", center=p.center)
+    v = p.potential_array()
+    psi0 = p.initial_states()
+    lat.set_potential(v)
+    lat.set_state(0, psi0[0])
+    lat.set_options(ortho_every=1, moments=False)
+    lat.step(2000)
+    hist = lat.history(2000)
+    got_e = np.array([h[0]["energy"] for h in hist])
+    ostates, ohist = orc.step(_olat(orc, lat), psi0, v, 2000)
+    ref_e = np.array([h[0]["energy"] for h in ohist])
+    assert np.abs(got_e - ref_e).max() / np.abs(ref_e).max() < 1e-10
+    final = lat.get_state(0)
+    assert _rel(final, ostates[0]) < 1e-10
+    assert abs(got_e[-1] - 1.0865202365) < 1e-8
+    lat.close()
+
+
+@pytest.mark.parametrize("n,kin,center,parity,ortho", [
+    (24, 3, "origin", (1, -1, -1), 1),
+    (16, 2, "cell", (0, 0, 0), 1),
+    (24, 1, "cell", (1, 0, -1), 3),
+    (12, 4, "origin", (0, 1, 0), 0),
+])
+def test_multistate_trajectory_fp64(itse, orc, n, kin, center, parity, ortho):
+    """Three states with reflection projections and Gram-Schmidt every `ortho` steps."""
+    a = 0.2
+    lat = _lat(itse, n, kin, True, "fp64", center, nstates=3, a=a, mass=1.3)
+    v = synth.potential_cornell(n, a, center, sigma=0.2, alpha=0.4)
+    states = synth.random_states(n, 3, seed=5)
+    lat.set_potential(v)
+    for i, s in enumerate(states):
+        lat.set_state(i, s)
+    lat.set_options(ortho_every=ortho, moments=True, parity=parity)
+    steps = 60
+    lat.step(steps)
+    hist = lat.history(steps)
+    ostates, ohist = orc.step(_olat(orc, lat), states, v, steps, ortho_every=ortho,
+                              parity=parity)
+    for s in range(steps):
+        for i in range(3):
+            for f in ("energy", "kinetic", "potential", "norm2", "x", "y", "z", "r2", "parity_even"):
+                g, r = hist[s][i][f], ohist[s][i][f]
+                assert abs(g - r) <= 1e-10 * max(1.0, abs(r)), (s, i, f, g, r)
+    for i in range(3):
+        assert _rel(lat.get_state(i), ostates[i]) < 1e-10
+    lat.close()
+
+
+def test_fp32_step_energies(itse, orc):
+    n, a = 32, 0.2
+    lat = _lat(itse, n, 3, True, "fp32", "origin", nstates=2, a=a)
+    v = synth.potential_cornell(n, a, "origin").astype(np.float32)
+    states = [s.astype(np.float32) for s in synth.random_states(n, 2, seed=9)]
+    lat.set_potential(v)
+    for i, s in enumerate(states):
+        lat.set_state(i, s)
+    lat.set_options(ortho_every=1, moments=True, parity=(1, -1))
+    lat.step(20)
+    hist = lat.history(20)
+    _, ohist = orc.step(_olat(orc, lat), [s.astype(np.float64) for s in states],
+                        v.astype(np.float64), 20, parity=(1, -1))
+    for s in range(20):
+        for i in range(2):
+            g, r = hist[s][i]["energy"], ohist[s][i]["energy"]
+            assert abs(g - r) <= 1e-5 * abs(r), (s, i, g, r)
+    lat.close()
+
+
+@pytest.mark.parametrize("center", ["cell", "origin"])
+def test_evaluate_moments(itse, orc, center):
+    n, a = 24, 0.15
+    lat = _lat(itse, n, 2, True, "fp64", center, nstates=2, a=a)
+    v = synth.potential_harmonic(n, a, center, 0.5)
+    states = synth.random_states(n, 2, seed=2)
+    states[1] = states[1] + 3.0 * np.exp(-((np.arange(n) - 5.0) ** 2) / 8.0)[:, None, None]
+    lat.set_potential(v)
+    for i, s in enumerate(states):
+        lat.set_state(i, s)
+    lat.evaluate(moments=True)
+    ref = orc.observe(_olat(orc, lat), states, v)
+    for i in range(2):
+        got = lat.observe(i)
+        for f in ("energy", "kinetic", "potential", "norm2", "x", "y", "z", "r2", "parity_even"):
+            assert abs(got[f] - ref[i][f]) <= 1e-11 * max(1.0, abs(ref[i][f])), (i, f)
+
+
+def test_project_and_orthogonalise(itse, orc):
+    n = 16
+    lat = _lat(itse, n, 1, True, "fp64", "cell", nstates=3)
+    states = synth.random_states(n, 3, seed=4)
+    for i, s in enumerate(states):
+        lat.set_state(i, s)
+    ol = _olat(orc, lat)
+    w = lat.project_parity(1, -1, 7)
+    pm = orc.project(ol, states[1], -1, 7)
+    assert abs(w - np.sum(pm * pm) / np.sum(states[1] ** 2)) < 1e-12
+    assert _rel(lat.get_state(1), pm / np.linalg.norm(pm)) < 1e-12
+    lat.orthogonalise(1)
+    lat.orthogonalise(2)
+    ref = orc.orthonormalise([states[0] / np.linalg.norm(states[0]), pm, states[2]])
+    # state 0 was never normalised by these calls: compare the orthogonal parts
+    g1 = lat.get_state(1)
+    g2 = lat.get_state(2)
+    assert abs(np.sum(g1 * states[0])) < 1e-10 * np.linalg.norm(states[0])
+    assert abs(np.sum(g2 * states[0])) < 1e-10 * np.linalg.norm(states[0])
+    assert abs(np.sum(g2 * g1)) < 1e-12
+    assert _rel(g2, ref[2]) < 1e-10
+    # axis reflection (INITSYMMETRY along x3)
+    w3 = lat.project_parity(0, +1, 4)
+    p3 = orc.project(ol, states[0], +1, 4)
+    assert abs(w3 - np.sum(p3 * p3) / np.sum(states[0] ** 2)) < 1e-12
+
+
+def test_batch_bitwise_equals_alone(itse):
+    """Lattices of several sizes and kinetic terms: stepping each alone and all in
+    one batch gives bitwise-identical states and energies."""
+    specs = [(16, 1, "fp64"), (24, 3, "fp64"), (32, 2, "fp32"), (24, 3, "fp32"), (16, 4, "fp32"),
+             (24, 3, "fp64")]
+    def build():
+        lats = []
+        for j, (n, kin, prec) in enumerate(specs):
+            a = 0.1
+            lat = _lat(itse, n, kin, True, prec, "origin", nstates=2, a=a, mass=1.0 + 0.3 * j)
+            v = synth.potential_cornell(n, a, "origin", sigma=0.1 + 0.02 * j)
+            lat.set_potential(v.astype(np.float32 if prec == "fp32" else np.float64))
+            for i, s in enumerate(synth.random_states(n, 2, seed=20 + j)):
+                lat.set_state(i, s.astype(np.float32 if prec == "fp32" else np.float64))
+            lat.set_options(ortho_every=1, parity=(1, 0) if j % 2 else (0, 0))
+            lats.append(lat)
+        return lats
+    alone = build()
+    for lat in alone:
+        lat.step(37)
+    mixed = build()
+    b = itse.Batch(mixed)
+    b.step(37)
+    for la, lb in zip(alone, mixed):
+        for i in range(2):
+            dt = np.float32 if la.precision == "fp32" else np.float64
+            assert np.array_equal(la.get_state(i, dt), lb.get_state(i, dt))
+            assert la.observe(i)["energy"] == lb.observe(i)["energy"]
+        assert la.step_count == lb.step_count == 37
+    b.close()
+
+
+def test_graph_replays_match_eager(itse, monkeypatch):
+    """Graph-replayed steps equal eagerly launched steps bitwise."""
+    n = 24
+    runs = []
+    for graphs in ("1", "0"):
+        monkeypatch.setenv("ITSE_GRAPHS", graphs)
+        lat = _lat(itse, n, 3, True, "fp32", "origin", nstates=2)
+        lat.set_potential(synth.potential_cornell(n, 0.1, "origin").astype(np.float32))
+        for i, s in enumerate(synth.random_states(n, 2, seed=3)):
+            lat.set_state(i, s.astype(np.float32))
+        lat.step(5)
+        lat.step(40)   # 2 chunk replays + 8 single-step replays
+        lat.sync()
+        runs.append([lat.get_state(i, np.float32) for i in range(2)])
+        runs[-1].append([h[0]["energy"] for h in lat.history(45)])
+        lat.close()
+    for a, b in zip(runs[0][:2], runs[1][:2]):
+        assert np.array_equal(a, b)
+    assert runs[0][2] == runs[1][2]
+
+
+def test_nonfinite_potential_rejected(itse):
+    n = 12
+    lat = _lat(itse, n)
+    v = np.zeros((n, n, n))
+    v[3, 4, 5] = np.nan
+    with pytest.raises(itse.ItseError) as e:
+        lat.set_potential(v)
+    assert e.value.status == -4
+    v[3, 4, 5] = -1e6
+    with pytest.raises(itse.ItseError) as e:
+        lat.set_potential(v)
+    assert e.value.status == -3
+    lat.close()
+
+
+def test_nonfinite_state_reported(itse):
+    n = 12
+    lat = _lat(itse, n)
+    psi = synth.random_state(n, 1)
+    psi[0, 0, 0] = np.inf
+    lat.set_state(0, psi)
+    lat.step(1)
+    with pytest.raises(itse.ItseError) as e:
+        lat.observe(0)
+    assert e.value.status == -4
+    lat.close()
