@@ -1,0 +1,180 @@
+"""Benchmark of the imaginary-time step on one MI355X.
+
+Workload (default): the precision-form solve at 256^3 - three states (parity
+even, odd, odd deflated against the odd one), FP32 wave-functions and transforms
+with FP64 norms/energies/Gram sums, relativistic lattice kinetic term
+sqrt(p^2+m^2)-m with m = 1.3, a = 0.025, dtau = a/4, Cornell potential
+-0.4/r + 0.2 r + 0.05 (x^2-y^2)/r (r >= a/2) stored as FP32, origin centring.
+
+A step = one application of the whole hot path to every state: transforms,
+kinetic multiply, update, parity projections, Gram-Schmidt, normalisation and
+energies.  value = site-steps/s counting each state's N^3 sites per step.
+
+Prints ONE JSON line (rank 0).  Extra keys: per-pass times and bytes, the same
+workload in FP64, the CPU oracle baseline on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def pass_bytes(n: int, w: int, nstates: int, parity, ortho: bool):
+    """Algorithmic bytes of each pass of one step (all states), from what each kernel
+    must read and write once: see the design doc, section 'Byte model'."""
+    sites = n ** 3
+    s = 2.0 * w * (n // 2 + 1) / n        # half-spectrum bytes per lattice site
+    k = nstates
+    nonzero_reads = sum((i + 1) if ortho else 1 for i in range(k))
+    out = {
+        "k_rows_fwd": sites * (nonzero_reads * w + k * w + k * s),
+        "k_cols<COL_FWD>": sites * k * 2 * s,
+        "k_cols<COL_KIN>": sites * k * 2 * s,
+        "k_cols<COL_INV>": sites * k * 2 * s,
+        "k_rows_inv": sites * k * (s + 3 * w),
+        "k_project": sites * sum(2 * w for i in range(k) if parity and parity[i]),
+        "k_gram": sites * k * w if (ortho and k > 1) else 0.0,
+        "k_finalize": 0.0,
+    }
+    return out
+
+
+def build_workload(n: int, fp32: bool):
+    import synth
+    p = synth.config_precision(n)
+    dt = np.float32 if fp32 else np.float64
+    v = p.potential_array(np.float64).astype(np.float32).astype(dt)  # FP32-stored potential
+    states = [s.astype(dt) for s in p.initial_states()]
+    return p, v, states
+
+
+def make_lattice(itse, p, v, states, fp32: bool):
+    lat = itse.Lattice(p.n, p.a, p.mass, p.dtau, kin=p.kin, subtract_rest_mass=p.subtract_rest_mass,
+                       precision="fp32" if fp32 else "fp64", center=p.center, nstates=p.nstates)
+    lat.set_potential(v)
+    for i, s in enumerate(states):
+        lat.set_state(i, s)
+    lat.set_options(ortho_every=p.ortho_every, moments=False, parity=list(p.parity))
+    return lat
+
+
+def timed_steps(torch, lat, steps: int, warmup: int):
+    lat.step(warmup)
+    lat.sync()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    stream = lat.stream
+    start.record(stream)
+    lat.step(steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    lat.sync()
+    return start.elapsed_time(stop) / 1000.0
+
+
+def cpu_baseline(p, v, states, budget_s: float = 30.0):
+    """The FP64 oracle on the same 256^3 workload, one step of all states."""
+    import oracle
+    L = oracle.lattice(p.n, p.a, p.mass, p.dtau, p.kin, p.subtract_rest_mass, p.center)
+    t0 = time.perf_counter()
+    oracle.step(L, [s.astype(np.float64) for s in states], v.astype(np.float64), 1,
+                parity=list(p.parity), record=False)
+    dt = time.perf_counter() - t0
+    sites = p.n ** 3 * p.nstates
+    return {"value": sites / dt, "unit": "site-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"1 step of all {p.nstates} states of the {p.n}^3 workload in FP64 ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=5)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs one lattice per GPU on a single GPU; "
+                                   "--gpus must be 1 (multi-GPU sharding is described in DESIGN.md, "
+                                   "not implemented)"}))
+        sys.exit(2)
+
+    import torch
+    import paper_2006_16935_amd as itse
+
+    torch.cuda.set_device(0)
+    n = args.n
+    p, v32, st32 = build_workload(n, fp32=True)
+    lat = make_lattice(itse, p, v32, st32, fp32=True)
+    secs = timed_steps(torch, lat, args.steps, args.warmup)
+    sites = n ** 3 * p.nstates
+    value = sites * args.steps / secs
+    ms_per_step = secs * 1000.0 / args.steps
+
+    # per-pass durations (HIP events between eager launches on the lattice stream)
+    prof = lat.profile_step(args.profile_steps)
+    pb = pass_bytes(n, 4, p.nstates, p.parity, p.ortho_every == 1)
+    dom = max(prof, key=lambda k: prof[k])
+    dom_ms = prof[dom]
+    achieved = pb[dom] / (dom_ms * 1e-3) / 1e9
+    step_bytes = sum(pb.values())
+    e_fp32 = [lat.observe(i)["energy"] for i in range(p.nstates)]
+    lat.close()
+
+    extra = {}
+    if not args.no_fp64:
+        p64, v64, st64 = build_workload(n, fp32=False)
+        lat64 = make_lattice(itse, p64, v64, st64, fp32=False)
+        steps64 = max(10, args.steps // 4)
+        secs64 = timed_steps(torch, lat64, steps64, max(2, args.warmup // 2))
+        extra["fp64_site_steps_per_s"] = sites * steps64 / secs64
+        extra["fp64_ms_per_step"] = secs64 * 1000.0 / steps64
+        lat64.close()
+
+    out = {
+        "metric": "site-steps/s at 256^3 (FP32 steps with FP64 reductions)",
+        "value": value,
+        "unit": "site-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"precision form: {n}^3, 3 states (parity +,-,- with Gram-Schmidt), "
+                               f"FP32 states/FFT, FP64 reductions, sqrt(p^2+m^2)-m, Cornell+aniso FP32 V",
+                   "n": n, "nstates": p.nstates, "site_steps_per_step": sites},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                     "kernel_ms": dom_ms, "kernel_bytes": pb[dom]},
+        "passes_ms": prof,
+        "passes_bytes": pb,
+        "step_bytes": step_bytes,
+        "step_hbm_frac": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "energies_fp32": e_fp32,
+    }
+    out.update(extra)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, v32.astype(np.float64), [s.astype(np.float64) for s in st32])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

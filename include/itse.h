@@ -190,6 +190,15 @@ itse_status itse_spectrum(itse_lattice *lat, int i, void *out_device);
  * Synchronises. */
 itse_status itse_polish(itse_lattice *lat, int i, itse_obs *out);
 
+/* Per-pass timing: `nsteps` steps launched eagerly with HIP events recorded
+ * between consecutive kernel launches on the lattice stream.  On input *npass is
+ * the capacity of ms_out; on output the number of passes per step, with
+ * ms_out[p] the mean duration of pass p.  `names` (optional) receives a JSON
+ * array of the pass kernel names.  The steps are real steps (the state advances).
+ * Synchronises. */
+itse_status itse_profile_step(itse_lattice *lat, int nsteps, double *ms_out, int *npass, char *names,
+                              size_t names_len);
+
 /* Wait for all work enqueued for the lattice; reports device-side errors. */
 itse_status itse_sync(itse_lattice *lat);
 

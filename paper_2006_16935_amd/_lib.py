@@ -93,6 +93,7 @@ def load():
         "itse_spectrum": ([vp, ip, vp], ip),
         "itse_polish": ([vp, ip, P(Obs)], ip),
         "itse_sync": ([vp], ip),
+        "itse_profile_step": ([vp, ip, P(dp), P(ip), ctypes.c_char_p, ctypes.c_size_t], ip),
         "itse_batch_create": ([ip, P(vp), vp, P(vp)], ip),
         "itse_batch_step": ([vp, ip], ip),
         "itse_batch_destroy": ([vp], ip),

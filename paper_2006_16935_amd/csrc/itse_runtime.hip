@@ -1030,3 +1030,64 @@ extern "C" itse_status itse_polish(itse_lattice *L, int i, itse_obs *out) {
     if (st) return st;
     return itse_observe(S, 0, out);
 }
+
+// ------------------------------------------------------------------------------------
+// Per-pass profiling (eager launches bracketed by events)
+// ------------------------------------------------------------------------------------
+namespace itse {
+template <typename R>
+static hipError_t launch_pass(const Group &g, int p, hipStream_t s) {
+    switch (p) {
+    case 0: return Launch<R>::rows_fwd(g.n, g.variant, g.jobs, g.njobs, s);
+    case 1: return Launch<R>::cols(g.n, g.variant, COL_FWD, 1, 0, g.jobs, g.njobs, s);
+    case 2: return Launch<R>::cols(g.n, g.variant, COL_KIN, 0, 1, g.jobs, g.njobs, s);
+    case 3: return Launch<R>::cols(g.n, g.variant, COL_INV, 1, 0, g.jobs, g.njobs, s);
+    case 4: return Launch<R>::rows_inv(g.n, g.variant, INV_UPDATE, g.jobs, g.njobs, s);
+    case 5: return Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, s);
+    case 6: return Launch<R>::gram(g.n, g.lats, g.nlats, 0, s);
+    default: return launch_finalize(g.lats, g.nlats, FIN_STEP, s);
+    }
+}
+static const char *pass_names[] = {"k_rows_fwd", "k_cols<COL_FWD>", "k_cols<COL_KIN>", "k_cols<COL_INV>",
+                                   "k_rows_inv", "k_project", "k_gram", "k_finalize"};
+constexpr int NPASS = 8;
+}  // namespace itse
+
+extern "C" itse_status itse_profile_step(itse_lattice *L, int nsteps, double *ms_out, int *npass, char *names,
+                                         size_t names_len) {
+    if (!L || !npass || (*npass > 0 && !ms_out)) return fail(ITSE_EINVAL, "null argument");
+    if (nsteps < 1) return fail(ITSE_EINVAL, "nsteps < 1");
+    Group g = single_group(L);
+    std::vector<hipEvent_t> ev((size_t)nsteps * (NPASS + 1));
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+    for (int s = 0; s < nsteps; ++s) {
+        HIPCHK(hipEventRecord(ev[(size_t)s * (NPASS + 1)], L->stream));
+        for (int p = 0; p < NPASS; ++p) {
+            hipError_t e = L->d.precision == ITSE_FP32 ? launch_pass<float>(g, p, L->stream)
+                                                       : launch_pass<double>(g, p, L->stream);
+            if (e != hipSuccess) return fail(ITSE_EDEVICE, "pass %d: %s", p, hipGetErrorString(e));
+            HIPCHK(hipEventRecord(ev[(size_t)s * (NPASS + 1) + p + 1], L->stream));
+        }
+    }
+    HIPCHK(hipStreamSynchronize(L->stream));
+    L->steps_host += nsteps;
+    const int cap = *npass;
+    for (int p = 0; p < NPASS && p < cap; ++p) {
+        double acc = 0.0;
+        for (int s = 0; s < nsteps; ++s) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ev[(size_t)s * (NPASS + 1) + p], ev[(size_t)s * (NPASS + 1) + p + 1]));
+            acc += ms;
+        }
+        ms_out[p] = acc / nsteps;
+    }
+    *npass = NPASS;
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (names && names_len) {
+        std::string js = "[";
+        for (int p = 0; p < NPASS; ++p) js += std::string(p ? ", " : "") + "\"" + pass_names[p] + "\"";
+        js += "]";
+        snprintf(names, names_len, "%s", js.c_str());
+    }
+    return check_device_error(L);
+}

@@ -231,6 +231,15 @@ class Lattice:
     def sync(self):
         check(self._L.itse_sync(self.h))
 
+    def profile_step(self, nsteps: int = 5):
+        """Mean duration (ms) of each pass of a step, measured with HIP events."""
+        import json
+        ms = (ctypes.c_double * 16)()
+        npass = ctypes.c_int(16)
+        names = ctypes.create_string_buffer(1024)
+        check(self._L.itse_profile_step(self.h, int(nsteps), ms, ctypes.byref(npass), names, 1024))
+        return dict(zip(json.loads(names.value.decode()), [ms[p] for p in range(npass.value)]))
+
 
 class Batch:
     """Independent lattices stepped together (one graph launch per chunk of steps)."""
