@@ -30,23 +30,21 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
 
 def pass_bytes(n: int, w: int, nstates: int, parity, ortho: bool):
-    """Algorithmic bytes of each pass of one step (all states), from what each kernel
-    must read and write once: see the design doc, section 'Byte model'."""
+    """Algorithmic bytes of each kernel of one step (all states): what each kernel
+    must read and write once.  States are kept as psi_i = sum_(j<=i) c_ji u_j, so
+    the two plane passes read i+1 arrays for state i when Gram-Schmidt is on."""
     sites = n ** 3
     s = 2.0 * w * (n // 2 + 1) / n        # half-spectrum bytes per lattice site
     k = nstates
-    nonzero_reads = sum((i + 1) if ortho else 1 for i in range(k))
-    out = {
-        "k_rows_fwd": sites * (nonzero_reads * w + k * w + k * s),
-        "k_cols<COL_FWD>": sites * k * 2 * s,
-        "k_cols<COL_KIN>": sites * k * 2 * s,
-        "k_cols<COL_INV>": sites * k * 2 * s,
-        "k_rows_inv": sites * k * (s + 3 * w),
+    reads = sum((i + 1) if ortho else 1 for i in range(k))
+    return {
+        "k_plane_fwd": sites * (reads * w + k * s),
+        "k_columns": sites * k * 2 * s,
+        "k_plane_inv": sites * (k * s + reads * w + k * w + k * w),
         "k_project": sites * sum(2 * w for i in range(k) if parity and parity[i]),
         "k_gram": sites * k * w if (ortho and k > 1) else 0.0,
         "k_finalize": 0.0,
     }
-    return out
 
 
 def build_workload(n: int, fp32: bool):

@@ -80,7 +80,7 @@ typedef enum { ITSE_DTYPE_F32 = 1, ITSE_DTYPE_F64 = 2 } itse_dtype;
 
 /* Lattice description (the paper's NUM, A, MASS, KINTERM, EPS). */
 typedef struct {
-    int n;                   /* points per axis; 8..512 with prime factors 2, 3 only */
+    int n;                   /* points per axis; 8..256 with prime factors 2, 3 only */
     double a;                /* lattice spacing A > 0                                 */
     double mass;             /* mass M > 0                                            */
     double dtau;             /* imaginary-time step EPS > 0                           */
@@ -129,7 +129,7 @@ const char *itse_version(void);
 /* Device bytes a lattice with this description holds (for admission control). */
 size_t itse_footprint_bytes(const itse_desc *desc);
 
-/* Create a lattice.  Checks n (factors 2, 3; 8..512), a, mass, dtau > 0, kin,
+/* Create a lattice.  Checks n (factors 2, 3; 8..256), a, mass, dtau > 0, kin,
  * nstates, and the stability bound dtau * max_k T(k) <= 1.95 (ITSE_EUNSTABLE).
  * `hip_stream` (hipStream_t, may be NULL for the null stream) orders all work.
  * `alloc`/`free_fn` may be NULL (then hipMalloc/hipFree).  States start at 0,

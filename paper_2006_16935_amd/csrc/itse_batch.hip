@@ -69,9 +69,11 @@ extern "C" itse_status itse_schedule_get(int n, int precision, char *json, size_
     Sched s = prec_schedule(n, precision, v);
     if (json && len) {
         snprintf(json, len,
-                 "{\"n\": %d, \"precision\": %d, \"variant\": %d, \"row_pairs\": %d, \"cols_per_wg\": %d, "
-                 "\"wg_rows\": %d, \"wg_cols\": %d}",
-                 n, precision, v, s.rows_rp, s.cols_w, s.nb_rows, s.nb_cols);
+                 "{\"n\": %d, \"precision\": %d, \"variant\": %d, \"variants\": %d, \"split\": %d, "
+                 "\"plane_waves\": %d, \"cols_per_wg\": %d, \"cols_waves\": %d, \"wg_plane\": %d, "
+                 "\"wg_cols\": %d, \"lds_plane\": %d, \"lds_cols\": %d}",
+                 n, precision, v, precision == ITSE_FP32 ? Launch<float>::variants(n) : Launch<double>::variants(n),
+                 s.split, s.nwp, s.cols_w, s.nwc, s.nb_rows, s.nb_cols, s.lds_plane, s.lds_cols);
     }
     return ITSE_OK;
 }
@@ -137,6 +139,7 @@ extern "C" itse_status itse_batch_create(int count, itse_lattice *const *lats, v
         g.njobs = (int)jobs.size();
         g.lats = dl;
         g.nlats = (int)lrefs.size();
+        for (auto *L : members) g.kmax = std::max(g.kmax, L->d.nstates);
         B->groups.push_back(g);
     }
     if (hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess)

@@ -21,8 +21,8 @@ enum ColQ { CQ_NORM = 0, CQ_PAR, NQC };
 
 // Modes of the inverse (update) pass.
 enum InvMode { INV_UPDATE = 0, INV_EVAL = 1, INV_KOUT = 2 };
-// Modes of the strided-axis transform pass.
-enum ColMode { COL_FWD = 0, COL_INV = 1, COL_KIN = 2 };
+// Modes of the column pass.
+enum ColMode { COL_FWD = 0, COL_KIN = 2 };
 // Modes of the finalisation kernel.
 enum FinMode { FIN_STEP = 0, FIN_EVAL = 1, FIN_NORM_ONLY = 2 };
 
@@ -40,8 +40,10 @@ struct LatDev {
     int n, nstates, kin, sub, center, prec;
     double a, mass, dtau, h;
     // buffers (element type follows prec)
-    void *u[MAXK];       // raw states after the last update
-    void *phi[MAXK];     // current states (materialised at the start of a step)
+    // raw states: two buffers per state, ub[(step + 0) & 1] holds the current raw
+    // arrays, ub[(step + 1) & 1] receives the update (so that the lazily combined
+    // current states stay readable while other states' updates are written)
+    void *ub[2][MAXK];
     void *spec[MAXK];    // half spectra
     void *v;             // potential
     const void *tw;      // twiddle table exp(-2 pi i e / n), n entries, prec
@@ -65,17 +67,26 @@ struct LatDev {
     ObsDev *hist;             // [HIST_CAP][MAXK]
 };
 
+// Raw state array j of the current step (which = 0) or of the step being formed
+// (which = 1).
+__host__ __device__ inline void *state_buf(const LatDev &L, long long step, int which, int j) {
+    return L.ub[(int)((step + which) & 1)][j];
+}
+
 struct JobRef {
     LatDev *lat;
     int state;
     int pad_;
 };
 
-// Kernel schedule for one (n, precision).
+// Kernel schedule for one (n, precision, variant).
 struct Sched {
-    int rows_rp;   // row pairs per workgroup in the row passes
-    int cols_w;    // columns per workgroup in the strided passes
-    int nb_rows, nb_cols, nb_proj, nb_gram;
+    int split;     // sub-planes per plane (y = r + split * j)
+    int nwp;       // waves per plane-pass workgroup
+    int cols_w;    // kz columns per column-pass workgroup
+    int nwc;       // waves per column-pass workgroup
+    int nb_rows, nb_cols, nb_proj, nb_gram;  // partial-sum blocks per state
+    int lds_plane, lds_cols;                 // LDS bytes of the two kinds of workgroup
 };
 
 // Per-precision launchers (defined in itse_f32.hip / itse_f64.hip).
@@ -85,14 +96,13 @@ struct Launch {
     static Sched schedule(int n, int variant);
     static int variants(int n);
     // Passes over a group of jobs sharing n; jobs is a device array of njobs entries.
-    static hipError_t rows_fwd(int n, int variant, const JobRef *jobs, int njobs, hipStream_t s);
-    static hipError_t cols(int n, int variant, int mode, int axis, int moments, const JobRef *jobs,
-                           int njobs, hipStream_t s);
-    static hipError_t rows_inv(int n, int variant, int mode, const JobRef *jobs, int njobs,
-                               hipStream_t s);
-    static hipError_t project(int n, const JobRef *jobs, int njobs, int force_sign, int force_axes,
+    static hipError_t plane_fwd(int n, int variant, const JobRef *jobs, int njobs, hipStream_t s);
+    static hipError_t columns(int n, int variant, int mode, int moments, const JobRef *jobs, int njobs, void *out,
                               hipStream_t s);
-    static hipError_t gram(int n, const JobRef *lats, int nlats, int force, hipStream_t s);
+    static hipError_t plane_inv(int n, int variant, int mode, const JobRef *jobs, int njobs, hipStream_t s);
+    static hipError_t project(int n, const JobRef *jobs, int njobs, int force_sign, int force_axes, int which,
+                              hipStream_t s);
+    static hipError_t gram(int n, int kmax, const JobRef *lats, int nlats, int force, int which, hipStream_t s);
     static hipError_t combine(int n, const JobRef *jobs, int njobs, void *const *outs, hipStream_t s);
     static hipError_t convert_in(const void *src, int src_dtype, void *dst, size_t count, hipStream_t s);
     static hipError_t convert_out(const void *src, void *dst, int dst_dtype, size_t count, hipStream_t s);
@@ -101,13 +111,12 @@ struct Launch {
 hipError_t launch_finalize(const JobRef *lats, int nlats, int mode, hipStream_t s);
 hipError_t launch_check_potential(const LatDev *lat, int prec, hipStream_t s);
 
-// Number of sites per thread in the flat (projection, Gram) kernels.
-constexpr int FLAT_SPT = 4;
-
+// Workgroups of the flat kernels (Gram sums, combination): a fixed count per n,
+// so that the partial-sum layout and the summation order do not change.
 inline int flat_blocks(int n) {
-    long long n3 = (long long)n * n * n;
-    long long per = (long long)NT * FLAT_SPT;
-    return (int)((n3 + per - 1) / per);
+    const long long n3 = (long long)n * n * n;
+    const long long b = (n3 + 4 * NT - 1) / (4 * NT);
+    return (int)(b < 1024 ? b : 1024);
 }
 
 }  // namespace itse

@@ -1,12 +1,62 @@
 // Host-side launchers for one precision; included by itse_f32.hip and itse_f64.hip.
 #pragma once
 
-#include "itse_kernels.h"
+#include "itse_pass.h"
 
 namespace itse {
 
-#define ITSE_FOR_EACH_N(X) \
-    X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+// Lattice sizes with compiled passes, and the schedule variants of each.
+#define ITSE_FOR_EACH_N(X) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+
+template <typename R, int N>
+struct NVariants {
+    static constexpr int value = 1;
+};
+template <>
+struct NVariants<float, 128> {
+    static constexpr int value = 2;
+};
+template <>
+struct NVariants<float, 256> {
+    static constexpr int value = 2;
+};
+template <>
+struct NVariants<double, 256> {
+    static constexpr int value = 2;
+};
+
+template <typename R, int N, int V>
+static Sched sched_of() {
+    using G = Geo<R, N, V>;
+    Sched s{};
+    s.split = G::S;
+    s.nwp = G::NWP;
+    s.cols_w = G::W;
+    s.nwc = G::NWC;
+    s.nb_rows = G::NB_PLANE;
+    s.nb_cols = G::NB_COLS;
+    s.nb_proj = N;
+    s.nb_gram = flat_blocks(N);
+    s.lds_plane = (int)(G::PLANE_ELEMS * sizeof(C2<R>) + N * sizeof(C2<R>));
+    s.lds_cols = (int)(N * G::CS * sizeof(C2<R>) + N * sizeof(C2<R>) + N * sizeof(double));
+    return s;
+}
+
+// Calls F.template operator()<N, V>() for the runtime (n, variant).
+template <typename R, typename F>
+static hipError_t dispatch(int n, int variant, F f) {
+    switch (n) {
+#define ITSE_CASE(NN)                                                                  \
+    case NN:                                                                           \
+        if (variant == 0 || NVariants<R, NN>::value == 1) return f.template operator()<NN, 0>(); \
+        if constexpr (NVariants<R, NN>::value > 1) return f.template operator()<NN, 1>(); \
+        return hipErrorInvalidValue;
+        ITSE_FOR_EACH_N(ITSE_CASE)
+#undef ITSE_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+}
 
 template <typename R>
 bool Launch<R>::supported(int n) {
@@ -22,108 +72,112 @@ bool Launch<R>::supported(int n) {
 
 template <typename R>
 int Launch<R>::variants(int n) {
-    return supported(n) ? 1 : 0;
+    switch (n) {
+#define ITSE_CASE(NN) \
+    case NN:          \
+        return NVariants<R, NN>::value;
+        ITSE_FOR_EACH_N(ITSE_CASE)
+#undef ITSE_CASE
+    default:
+        return 0;
+    }
 }
+
+template <typename R>
+struct SchedF {
+    Sched *o;
+    template <int N, int V>
+    hipError_t operator()() {
+        *o = sched_of<R, N, V>();
+        return hipSuccess;
+    }
+};
 
 template <typename R>
 Sched Launch<R>::schedule(int n, int variant) {
-    (void)variant;
-    Sched s{};
-    switch (n) {
-#define ITSE_CASE(NN)                                                      \
-    case NN:                                                               \
-        s.rows_rp = RowSched<NN>::RP;                                      \
-        s.cols_w = ColW<R>::W;                                             \
-        s.nb_rows = RowSched<NN>::NB;                                      \
-        s.nb_cols = ColSched<R, NN, ColW<R>::W>::NB;                       \
-        break;
-        ITSE_FOR_EACH_N(ITSE_CASE)
-#undef ITSE_CASE
-    default:
-        break;
-    }
-    s.nb_proj = flat_blocks(n);
-    s.nb_gram = flat_blocks(n);
-    return s;
+    Sched out{};
+    (void)dispatch<R>(n, variant, SchedF<R>{&out});
+    return out;
 }
 
 template <typename R>
-hipError_t Launch<R>::rows_fwd(int n, int variant, const JobRef *jobs, int njobs, hipStream_t s) {
-    (void)variant;
+struct PlaneFwdF {
+    const JobRef *jobs;
+    int njobs;
+    hipStream_t s;
+    template <int N, int V>
+    hipError_t operator()() {
+        using G = Geo<R, N, V>;
+        hipLaunchKernelGGL((k_plane_fwd<R, N, V>), dim3(G::NB_PLANE, njobs), dim3(G::NTP), 0, s, jobs);
+        return hipGetLastError();
+    }
+};
+
+template <typename R>
+hipError_t Launch<R>::plane_fwd(int n, int variant, const JobRef *jobs, int njobs, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    switch (n) {
-#define ITSE_CASE(NN)                                                                            \
-    case NN:                                                                                     \
-        hipLaunchKernelGGL((k_rows_fwd<R, NN>), dim3(RowSched<NN>::NB, njobs), dim3(NT), 0, s, jobs); \
-        break;
-        ITSE_FOR_EACH_N(ITSE_CASE)
-#undef ITSE_CASE
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <typename R, int NN>
-static void launch_cols_n(int mode, int axis, int moments, const JobRef *jobs, int njobs, hipStream_t s) {
-    constexpr int W = ColW<R>::W;
-    const dim3 grid(ColSched<R, NN, W>::NB, njobs);
-    if (mode == COL_FWD)
-        hipLaunchKernelGGL((k_cols<R, NN, W, COL_FWD>), grid, dim3(NT), 0, s, jobs, axis, moments);
-    else if (mode == COL_INV)
-        hipLaunchKernelGGL((k_cols<R, NN, W, COL_INV>), grid, dim3(NT), 0, s, jobs, axis, moments);
-    else
-        hipLaunchKernelGGL((k_cols<R, NN, W, COL_KIN>), grid, dim3(NT), 0, s, jobs, axis, moments);
+    return dispatch<R>(n, variant, PlaneFwdF<R>{jobs, njobs, s});
 }
 
 template <typename R>
-hipError_t Launch<R>::cols(int n, int variant, int mode, int axis, int moments, const JobRef *jobs, int njobs,
-                           hipStream_t s) {
-    (void)variant;
-    if (njobs <= 0) return hipSuccess;
-    switch (n) {
-#define ITSE_CASE(NN)                                                  \
-    case NN:                                                           \
-        launch_cols_n<R, NN>(mode, axis, moments, jobs, njobs, s);     \
-        break;
-        ITSE_FOR_EACH_N(ITSE_CASE)
-#undef ITSE_CASE
-    default:
-        return hipErrorInvalidValue;
+struct ColumnsF {
+    int mode, moments;
+    const JobRef *jobs;
+    int njobs;
+    void *out;
+    hipStream_t s;
+    template <int N, int V>
+    hipError_t operator()() {
+        using G = Geo<R, N, V>;
+        hipLaunchKernelGGL((k_columns<R, N, V>), dim3(G::NB_COLS, njobs), dim3(G::NTC), 0, s, jobs, mode, moments,
+                           (C2<R> *)out);
+        return hipGetLastError();
     }
-    return hipGetLastError();
-}
+};
 
 template <typename R>
-hipError_t Launch<R>::rows_inv(int n, int variant, int mode, const JobRef *jobs, int njobs, hipStream_t s) {
-    (void)variant;
-    if (njobs <= 0) return hipSuccess;
-    switch (n) {
-#define ITSE_CASE(NN)                                                                                   \
-    case NN:                                                                                            \
-        hipLaunchKernelGGL((k_rows_inv<R, NN>), dim3(RowSched<NN>::NB, njobs), dim3(NT), 0, s, jobs, mode); \
-        break;
-        ITSE_FOR_EACH_N(ITSE_CASE)
-#undef ITSE_CASE
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <typename R>
-hipError_t Launch<R>::project(int n, const JobRef *jobs, int njobs, int force_sign, int force_axes,
+hipError_t Launch<R>::columns(int n, int variant, int mode, int moments, const JobRef *jobs, int njobs, void *out,
                               hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_project<R>), dim3(flat_blocks(n), njobs), dim3(NT), 0, s, jobs, force_sign,
-                       force_axes);
+    return dispatch<R>(n, variant, ColumnsF<R>{mode, moments, jobs, njobs, out, s});
+}
+
+template <typename R>
+struct PlaneInvF {
+    int mode;
+    const JobRef *jobs;
+    int njobs;
+    hipStream_t s;
+    template <int N, int V>
+    hipError_t operator()() {
+        using G = Geo<R, N, V>;
+        hipLaunchKernelGGL((k_plane_inv<R, N, V>), dim3(G::NB_PLANE, njobs), dim3(G::NTP), 0, s, jobs, mode);
+        return hipGetLastError();
+    }
+};
+
+template <typename R>
+hipError_t Launch<R>::plane_inv(int n, int variant, int mode, const JobRef *jobs, int njobs, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    return dispatch<R>(n, variant, PlaneInvF<R>{mode, jobs, njobs, s});
+}
+
+template <typename R>
+hipError_t Launch<R>::project(int n, const JobRef *jobs, int njobs, int force_sign, int force_axes, int which,
+                              hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_project<R>), dim3(n, njobs), dim3(NT), 0, s, jobs, force_sign, force_axes, which);
     return hipGetLastError();
 }
 
 template <typename R>
-hipError_t Launch<R>::gram(int n, const JobRef *lats, int nlats, int force, hipStream_t s) {
-    if (nlats <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_gram<R>), dim3(flat_blocks(n), nlats), dim3(NT), 0, s, lats, force);
+hipError_t Launch<R>::gram(int n, int kmax, const JobRef *lats, int nlats, int force, int which, hipStream_t s) {
+    if (nlats <= 0 || kmax < 2) return hipSuccess;
+    const dim3 grid(flat_blocks(n), nlats);
+    if (kmax <= 2) hipLaunchKernelGGL((k_gram<R, 2>), grid, dim3(NT), 0, s, lats, force, which);
+    else if (kmax <= 3) hipLaunchKernelGGL((k_gram<R, 3>), grid, dim3(NT), 0, s, lats, force, which);
+    else if (kmax <= 4) hipLaunchKernelGGL((k_gram<R, 4>), grid, dim3(NT), 0, s, lats, force, which);
+    else hipLaunchKernelGGL((k_gram<R, MAXK>), grid, dim3(NT), 0, s, lats, force, which);
     return hipGetLastError();
 }
 

@@ -1,0 +1,588 @@
+// Device code of the three-pass imaginary-time step (included once per
+// precision by itse_f32.hip / itse_f64.hip).
+//
+// The step applies, per state, psi' = A psi - B dtau H_K psi with
+// H_K psi = IFFT[T(k) FFT[psi]] / N^3 (the paper's equation iter_proced and its
+// kinetic terms H_K^(1..3)).  The 3D transform is split over three passes that
+// each read and write HBM once:
+//
+//   P1 (plane, forward)  sub-plane (x, r) = rows y = r + S j of plane x:
+//                        R2C along z (two real rows packed as one complex row),
+//                        complex FFT of length M = N/S along j.
+//   P2 (columns)         for (y', kz-chunk): radix-S combination of the S
+//                        sub-spectra (completing the y transform), FFT along x,
+//                        multiply by T(k)/N^3 (FP64 symbol and product), inverse
+//                        FFT along x, inverse radix-S split.
+//   P3 (plane, inverse)  length-M inverse FFT along j, C2R along z, then the
+//                        update and FP64 partial sums of <psi|psi>, <psi|K psi>,
+//                        <psi|V psi>, <psi'|psi'> (and moments).
+//
+// The split of the y axis: with y = r + S j and ky = ky' + M q,
+//   X[ky' + M q] = sum_r w_S^(r q) w_N^(r ky') S_r[ky'],  S_r[ky'] = sum_j x_(r+Sj) w_M^(j ky'),
+// and the inverse mirrors it.  Spectrum storage per state: S sub-spectra
+// [r][x][ky'][kz], kz = 0..N/2 (private to these passes).
+//
+// Current states are kept lazily: psi_i = sum_(j<=i) coef[j][i] u_j, formed in
+// FP64 from the raw updated arrays u_j on every load (normalisation and
+// Gram-Schmidt cost no extra pass).
+#pragma once
+
+#include "itse_fft.h"
+#include "itse_internal.h"
+
+namespace itse {
+
+// ---------------------------------------------------------------------------
+// Schedules: split factor S (sub-planes per plane), waves per workgroup in the
+// plane passes (NWP) and the column pass (NWC), kz columns per column-pass
+// workgroup (W).  Variant V selects among
+// the alternatives the autotuner times.
+// ---------------------------------------------------------------------------
+template <typename R, int N, int V>
+struct Plan;
+
+#define ITSE_PLAN(RT, NN, VV, S_, NWP_, W_, NWC_)                 \
+    template <>                                                   \
+    struct Plan<RT, NN, VV> {                                     \
+        static constexpr int S = S_, NWP = NWP_, W = W_, NWC = NWC_; \
+    };
+
+// FP32: variant 0 is the default.
+ITSE_PLAN(float, 8, 0, 1, 1, 5, 1)
+ITSE_PLAN(float, 12, 0, 1, 1, 7, 1)
+ITSE_PLAN(float, 16, 0, 1, 2, 9, 1)
+ITSE_PLAN(float, 24, 0, 1, 2, 13, 1)
+ITSE_PLAN(float, 32, 0, 1, 4, 17, 1)
+ITSE_PLAN(float, 48, 0, 1, 4, 16, 1)
+ITSE_PLAN(float, 64, 0, 1, 4, 16, 1)
+ITSE_PLAN(float, 96, 0, 1, 4, 16, 2)
+ITSE_PLAN(float, 128, 0, 1, 8, 16, 2)
+ITSE_PLAN(float, 192, 0, 2, 8, 8, 4)
+ITSE_PLAN(float, 256, 0, 4, 8, 8, 8)
+ITSE_PLAN(float, 256, 1, 2, 8, 16, 8)
+ITSE_PLAN(float, 128, 1, 2, 4, 8, 2)
+// FP64
+ITSE_PLAN(double, 8, 0, 1, 1, 5, 1)
+ITSE_PLAN(double, 12, 0, 1, 1, 7, 1)
+ITSE_PLAN(double, 16, 0, 1, 2, 9, 1)
+ITSE_PLAN(double, 24, 0, 1, 2, 13, 1)
+ITSE_PLAN(double, 32, 0, 1, 4, 17, 1)
+ITSE_PLAN(double, 48, 0, 1, 4, 8, 1)
+ITSE_PLAN(double, 64, 0, 1, 4, 8, 1)
+ITSE_PLAN(double, 96, 0, 1, 4, 8, 2)
+ITSE_PLAN(double, 128, 0, 2, 4, 8, 2)
+ITSE_PLAN(double, 192, 0, 4, 4, 4, 4)
+ITSE_PLAN(double, 256, 0, 4, 8, 4, 4)
+ITSE_PLAN(double, 256, 1, 8, 4, 4, 8)
+#undef ITSE_PLAN
+
+template <typename R, int N, int V>
+struct Geo {
+    using PL = Plan<R, N, V>;
+    static constexpr int S = PL::S, NWP = PL::NWP, W = PL::W, NWC = PL::NWC;
+    static constexpr int H = N / 2 + 1;
+    static constexpr int M = N / S;
+    static constexpr int PAIRS = M / 2;
+    static_assert(M % 2 == 0, "sub-planes hold pairs of rows");
+    static_assert(PAIRS % NWP == 0, "pairs split evenly over waves");
+    static_assert((N / 2) % NWP == 0, "columns split evenly over waves");
+    static constexpr int PPW = PAIRS / NWP;     // row pairs per wave
+    static constexpr int CPW = (N / 2) / NWP;   // kz columns per wave (the kz = N/2 column extra)
+    // Row stride of the plane layout: room for a padded z transform in two rows
+    // (2 HP >= span), and HP = 8 mod 16 (FP32) or 4 mod 8 (FP64) so that the
+    // rows fall on different banks.
+    static constexpr int SPANZ = WaveFft<R, N, 1, -1, false, 1>::SPAN;
+    static constexpr int HMIN = (SPANZ + 1) / 2 > H ? (SPANZ + 1) / 2 : H;
+    static constexpr int HMOD = sizeof(R) == 4 ? 16 : 8;
+    static constexpr int HOFF = sizeof(R) == 4 ? 8 : 4;
+    static constexpr int HP = HMIN + ((HOFF - HMIN % HMOD) + HMOD) % HMOD;
+    static constexpr int LSZ = 2 * HP;
+    static constexpr int PLANE_ELEMS = M * HP;
+    static constexpr int NTP = 64 * NWP;
+    // Column pass
+    static constexpr int NCH = (H + W - 1) / W;      // kz chunks
+    static constexpr int LINES = S * W;              // x lines per column workgroup
+    static_assert(LINES % NWC == 0, "lines split evenly over waves");
+    static constexpr int LPWC = LINES / NWC;
+    static constexpr int CS = LINES + 1;  // row stride (x) in the column layout
+    static constexpr int NTC = 64 * NWC;
+    static constexpr int NB_PLANE = N * S;           // plane workgroups per state
+    static constexpr int NB_COLS = M * NCH;          // column workgroups per state
+};
+
+// Coordinate of index idx about the potential centre (cell centre (n-1)/2, or
+// origin with minimum image).
+__device__ __forceinline__ double site_coord(int idx, int n, int center, double a) {
+    if (center == ITSE_CENTER_CELL) return ((double)idx - 0.5 * (double)(n - 1)) * a;
+    return (double)((2 * idx <= n) ? idx : idx - n) * a;
+}
+
+__device__ __forceinline__ int mirror_idx(int idx, int n, int center) {
+    return center == ITSE_CENTER_CELL ? n - 1 - idx : (idx == 0 ? 0 : n - idx);
+}
+
+// Kinetic symbol from the sum of the three per-axis table entries (FP64):
+// non-relativistic forms use the sum directly; relativistic ones
+// sqrt(p^2 + m^2), or p^2 / (sqrt(p^2 + m^2) + m) = sqrt(p^2 + m^2) - m without
+// cancellation.
+__device__ __forceinline__ double kin_symbol(int kin, int sub, double mass, double s) {
+    if (kin == ITSE_KIN_NR_CONT || kin == ITSE_KIN_NR_LAT) return s;
+    const double e = sqrt(s + mass * mass);
+    return sub ? s / (e + mass) : e;
+}
+
+// Wave-level fixed-order sum of a double over the 64 lanes (lane 0 gets it).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Fixed-order workgroup sums of Q doubles; thread 0 writes dst[0..Q).
+template <int Q, int NTH>
+__device__ __forceinline__ void block_sums(double (&acc)[Q], double *dst, double *lds) {
+    constexpr int NWV = NTH / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const double s = wave_sum(acc[q]);
+        if (lane == 0) lds[q * NWV + wv] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < Q) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NWV; ++w) s += lds[threadIdx.x * NWV + w];
+        dst[threadIdx.x] = s;
+    }
+}
+
+// Lattice fields used by the passes, copied out of the device record once.
+template <typename R>
+struct LatView {
+    const R *u[MAXK];
+    double c[MAXK];
+    int i;
+};
+
+template <typename R>
+__device__ __forceinline__ void load_view(LatView<R> &vw, const LatDev &L, int i) {
+    vw.i = i;
+#pragma unroll
+    for (int j = 0; j < MAXK; ++j) {
+        vw.u[j] = (const R *)state_buf(L, L.step, 0, j);
+        vw.c[j] = (j <= i) ? L.coef[j][i] : 0.0;
+    }
+}
+
+// Current state psi_i at flat offset off: sum_(j<=i) coef[j][i] u_j in FP64,
+// rounded once to the storage precision.
+template <typename R>
+__device__ __forceinline__ R lazy_psi(const LatView<R> &vw, size_t off) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < MAXK; ++j)
+        if (j <= vw.i && vw.c[j] != 0.0) s += vw.c[j] * (double)vw.u[j][off];
+    return (R)s;
+}
+
+// ---------------------------------------------------------------------------
+// P1: forward plane pass.  grid.x = x * S + r, grid.y = job.
+// ---------------------------------------------------------------------------
+template <typename R, int N, int V>
+__global__ void __launch_bounds__((Geo<R, N, V>::NTP)) k_plane_fwd(const JobRef *__restrict__ jobs) {
+    using G = Geo<R, N, V>;
+    constexpr int S = G::S, M = G::M, H = G::H, HP = G::HP, LSZ = G::LSZ, PPW = G::PPW, CPW = G::CPW;
+    __shared__ C2<R> buf[G::PLANE_ELEMS];
+    __shared__ C2<R> tw[N];
+    const JobRef job = jobs[blockIdx.y];
+    const LatDev &L = *job.lat;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int x = blockIdx.x / S, r = blockIdx.x % S;
+    const C2<R> *twg = (const C2<R> *)L.tw;
+    for (int e = tid; e < N; e += G::NTP) tw[e] = twg[e];
+    LatView<R> vw;
+    load_view(vw, L, job.state);
+    C2<R> *spec = (C2<R> *)L.spec[job.state];
+
+    // rows of this wave's pairs -> packed complex rows (z along the line)
+    const int p0 = wv * PPW;
+    for (int e = lane; e < PPW * N; e += 64) {
+        const int pl = e / N, z = e % N;
+        const int p = p0 + pl;
+        const int y0 = r + S * (2 * p), y1 = y0 + S;
+        const size_t o0 = ((size_t)x * N + y0) * N + z, o1 = ((size_t)x * N + y1) * N + z;
+        buf[p * LSZ + z] = C2<R>{lazy_psi(vw, o0), lazy_psi(vw, o1)};
+    }
+    __syncthreads();  // twiddles
+    WaveFft<R, N, PPW, -1, false, 1>::run(buf + p0 * LSZ, LSZ, 1, tw, lane);
+    // unpack each pair into two half spectra, in place: rows 2p, 2p+1 of the plane layout
+    constexpr int TU = (H + 63) / 64;
+    for (int pl = 0; pl < PPW; ++pl) {
+        C2<R> *zl = buf + (p0 + pl) * LSZ;
+        C2<R> a0[TU], a1[TU];
+#pragma unroll
+        for (int t = 0; t < TU; ++t) {
+            const int k = lane + 64 * t;
+            if (k < H) {
+                const C2<R> ck = zl[k];
+                const C2<R> cm = zl[(N - k) % N];
+                a0[t] = C2<R>{(R)0.5 * (ck.x + cm.x), (R)0.5 * (ck.y - cm.y)};
+                a1[t] = C2<R>{(R)0.5 * (ck.y + cm.y), (R)0.5 * (cm.x - ck.x)};
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int t = 0; t < TU; ++t) {
+            const int k = lane + 64 * t;
+            if (k < H) {
+                zl[k] = a0[t];
+                zl[HP + k] = a1[t];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // transform along j (rows) for this wave's kz columns, the kz = N/2 column by the last wave
+    WaveFft<R, M, CPW, -1, true, S>::run(buf + wv * CPW, 1, HP, tw, lane);
+    if (wv == G::NWP - 1) WaveFft<R, M, 1, -1, true, S>::run(buf + N / 2, 1, HP, tw, lane);
+    __syncthreads();
+    C2<R> *dst = spec + ((size_t)r * N + x) * M * H;
+    for (int e = tid; e < M * H; e += G::NTP) {
+        const int ky = e / H, kz = e % H;
+        dst[e] = buf[ky * HP + kz];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P2: column pass.  grid.x = ky' * NCH + chunk, grid.y = job.
+// mode COL_KIN: forward x transform, kinetic multiply (+ parity-weight sums
+// when moments are on), inverse, back to sub-spectra.
+// mode COL_FWD: forward x transform only, stored in the standard layout
+// [kx][ky][kz] at `out` (for the spectrum query).
+// ---------------------------------------------------------------------------
+template <typename R, int N, int V>
+__global__ void __launch_bounds__((Geo<R, N, V>::NTC)) k_columns(const JobRef *__restrict__ jobs, int mode,
+                                                              int moments, C2<R> *__restrict__ out) {
+    using G = Geo<R, N, V>;
+    constexpr int S = G::S, M = G::M, H = G::H, W = G::W, CS = G::CS, LPW = G::LPWC, NTC = G::NTC;
+    __shared__ C2<R> buf[N * CS];
+    __shared__ C2<R> tw[N];
+    __shared__ double ktab[N];
+    __shared__ double red[NQC * (NTC / 64)];
+    const JobRef job = jobs[blockIdx.y];
+    const LatDev &L = *job.lat;
+    const int i = job.state;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int kyp = blockIdx.x / G::NCH, kz0 = (blockIdx.x % G::NCH) * W;
+    const C2<R> *twg = (const C2<R> *)L.tw;
+    for (int e = tid; e < N; e += NTC) {
+        tw[e] = twg[e];
+        ktab[e] = L.ktab[e];
+    }
+    __syncthreads();
+    C2<R> *spec = (C2<R> *)L.spec[i];
+    const size_t sub = (size_t)N * M * H;  // one sub-spectrum
+    // load S sub-spectra values, combine over r -> S full-y columns ky = ky' + M q
+    for (int e = tid; e < N * W; e += NTC) {
+        const int xx = e / W, w = e % W, kz = kz0 + w;
+        C2<R> v[S];
+        if (kz < H) {
+            const size_t base = ((size_t)xx * M + kyp) * H + kz;
+#pragma unroll
+            for (int rr = 0; rr < S; ++rr) {
+                C2<R> a = spec[rr * sub + base];
+                if (rr > 0) a = cmul(a, tw[rr * kyp]);
+                v[rr] = a;
+            }
+            Dft<S, -1, R>::run(v);
+        } else {
+#pragma unroll
+            for (int rr = 0; rr < S; ++rr) v[rr] = C2<R>{(R)0, (R)0};
+        }
+#pragma unroll
+        for (int q = 0; q < S; ++q) buf[xx * CS + q * W + w] = v[q];
+    }
+    __syncthreads();
+    const int l0 = wv * LPW;
+    WaveFft<R, N, LPW, -1, true, 1>::run(buf + l0, 1, CS, tw, lane);
+    if (mode == COL_FWD) {
+        __syncthreads();
+        for (int e = tid; e < N * S * W; e += NTC) {
+            const int xx = e / (S * W), l = e % (S * W), q = l / W, w = l % W, kz = kz0 + w;
+            if (kz < H) out[((size_t)xx * N + kyp + M * q) * H + kz] = buf[xx * CS + l];
+        }
+        return;
+    }
+    // kinetic multiply on this wave's lines: T(kx, ky, kz) / N^3 in FP64
+    const double inv_n3 = 1.0 / ((double)N * (double)N * (double)N);
+    const bool mom = moments && L.moments;
+    double acc[NQC] = {0.0, 0.0};
+    for (int e = lane; e < N * LPW; e += 64) {
+        const int xx = e / LPW, l = l0 + e % LPW, q = l / W, kz = kz0 + l % W;
+        if (kz >= H) continue;
+        const int ky = kyp + M * q;
+        C2<R> val = buf[xx * CS + l];
+        if (mom) {
+            // weight 2 for the interior of the half spectrum (its mirror is implied)
+            const double wt = (kz == 0 || 2 * kz == N) ? 1.0 : 2.0;
+            const double re = (double)val.x, im = (double)val.y;
+            acc[CQ_NORM] += wt * (re * re + im * im);
+            // <psi|P psi> = sum_k e^{i kappa} conj(psi_k)^2 / N^3 with kappa = 2 pi (kx+ky+kz)/N
+            // for the off-grid centre (x -> N-1-x), kappa = 0 for the origin
+            double pr = re * re - im * im;
+            const double pim = -2.0 * re * im;
+            if (L.center == ITSE_CENTER_CELL) {
+                const int mm = (xx + ky + kz) % N;
+                double sn, cs;
+                sincospi(2.0 * (double)mm / (double)N, &sn, &cs);
+                pr = cs * pr - sn * pim;
+            }
+            acc[CQ_PAR] += wt * pr;
+        }
+        const double t = kin_symbol(L.kin, L.sub, L.mass, ktab[xx] + ktab[ky] + ktab[kz]) * inv_n3;
+        val.x = (R)((double)val.x * t);
+        val.y = (R)((double)val.y * t);
+        buf[xx * CS + l] = val;
+    }
+    __builtin_amdgcn_wave_barrier();
+    WaveFft<R, N, LPW, +1, true, 1>::run(buf + l0, 1, CS, tw, lane);
+    if (mom) block_sums<NQC, NTC>(acc, L.part_cols + ((size_t)i * L.nb_cols + blockIdx.x) * NQC, red);
+    __syncthreads();
+    for (int e = tid; e < N * W; e += NTC) {
+        const int xx = e / W, w = e % W, kz = kz0 + w;
+        if (kz >= H) continue;
+        C2<R> v[S];
+#pragma unroll
+        for (int q = 0; q < S; ++q) v[q] = buf[xx * CS + q * W + w];
+        Dft<S, +1, R>::run(v);
+        const size_t base = ((size_t)xx * M + kyp) * H + kz;
+#pragma unroll
+        for (int rr = 0; rr < S; ++rr) {
+            C2<R> a = v[rr];
+            if (rr > 0) a = cmul(a, cconj(tw[rr * kyp]));
+            spec[rr * sub + base] = a;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// P3: inverse plane pass + update.  grid.x = x * S + r, grid.y = job.
+// mode INV_UPDATE: u_i <- ((1 - h V) psi - dtau K psi) / (1 + h V)   (= A psi - B dtau K psi)
+// mode INV_EVAL: sums only; INV_KOUT: K psi written to L.kout.
+// ---------------------------------------------------------------------------
+template <typename R, int N, int V>
+__global__ void __launch_bounds__((Geo<R, N, V>::NTP)) k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
+    using G = Geo<R, N, V>;
+    constexpr int S = G::S, M = G::M, H = G::H, HP = G::HP, LSZ = G::LSZ, PPW = G::PPW, CPW = G::CPW;
+    constexpr int NTP = G::NTP;
+    __shared__ C2<R> buf[G::PLANE_ELEMS];
+    __shared__ C2<R> tw[N];
+    __shared__ double red[NQR * (NTP / 64)];
+    const JobRef job = jobs[blockIdx.y];
+    const LatDev &L = *job.lat;
+    const int i = job.state;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int x = blockIdx.x / S, r = blockIdx.x % S;
+    const C2<R> *twg = (const C2<R> *)L.tw;
+    for (int e = tid; e < N; e += NTP) tw[e] = twg[e];
+    const C2<R> *src = (const C2<R> *)L.spec[i] + ((size_t)r * N + x) * M * H;
+    for (int e = tid; e < M * H; e += NTP) {
+        const int ky = e / H, kz = e % H;
+        buf[ky * HP + kz] = src[e];
+    }
+    __syncthreads();
+    WaveFft<R, M, CPW, +1, true, S>::run(buf + wv * CPW, 1, HP, tw, lane);
+    if (wv == G::NWP - 1) WaveFft<R, M, 1, +1, true, S>::run(buf + N / 2, 1, HP, tw, lane);
+    __syncthreads();
+    // pack rows 2p, 2p+1 (half spectra along z) into one complex row, in place
+    const int p0 = wv * PPW;
+    constexpr int TK = (N + 63) / 64;
+    for (int pl = 0; pl < PPW; ++pl) {
+        C2<R> *zl = buf + (p0 + pl) * LSZ;
+        C2<R> zz[TK];
+#pragma unroll
+        for (int t = 0; t < TK; ++t) {
+            const int k = lane + 64 * t;
+            if (N % 64 == 0 || k < N) {
+                const bool direct = 2 * k <= N;
+                const int kk = direct ? k : N - k;
+                C2<R> A = zl[kk], B = zl[HP + kk];
+                if (!direct) {
+                    A.y = -A.y;
+                    B.y = -B.y;
+                } else if (k == 0 || 2 * k == N) {
+                    A.y = (R)0;
+                    B.y = (R)0;
+                }
+                zz[t] = C2<R>{A.x - B.y, A.y + B.x};
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int t = 0; t < TK; ++t) {
+            const int k = lane + 64 * t;
+            if (N % 64 == 0 || k < N) zl[k] = zz[t];
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    WaveFft<R, N, PPW, +1, false, 1>::run(buf + p0 * LSZ, LSZ, 1, tw, lane);
+    // update of this wave's rows
+    LatView<R> vw;
+    load_view(vw, L, i);
+    const R *v = (const R *)L.v;
+    R *u = (R *)state_buf(L, L.step, 1, i);
+    R *kout = (R *)L.kout;
+    const R h = (R)L.h, dt = (R)L.dtau;
+    const bool mom = L.moments != 0;
+    const int center = L.center;
+    const double a = L.a;
+    double acc[NQR];
+#pragma unroll
+    for (int q = 0; q < NQR; ++q) acc[q] = 0.0;
+    for (int e = lane; e < PPW * N; e += 64) {
+        const int pl = e / N, z = e % N;
+        const int p = p0 + pl;
+        const C2<R> kp = buf[p * LSZ + z];
+#pragma unroll
+        for (int row = 0; row < 2; ++row) {
+            const int y = r + S * (2 * p + row);
+            const size_t off = ((size_t)x * N + y) * N + z;
+            const R kv = row == 0 ? kp.x : kp.y;
+            const R ph = lazy_psi(vw, off);
+            const R vv = v[off];
+            const R hv = h * vv;
+            const R un = (ph * ((R)1 - hv) - dt * kv) / ((R)1 + hv);
+            if (mode == INV_UPDATE) u[off] = un;
+            else if (mode == INV_KOUT) kout[off] = kv;
+            const double pd = (double)ph;
+            acc[RQ_PP] += pd * pd;
+            acc[RQ_PK] += pd * (double)kv;
+            acc[RQ_VPP] += (double)vv * pd * pd;
+            acc[RQ_UU] += (double)un * (double)un;
+            if (mom) {
+                const double cx = site_coord(x, N, center, a);
+                const double cy = site_coord(y, N, center, a);
+                const double cz = site_coord(z, N, center, a);
+                const double w2 = pd * pd;
+                acc[RQ_X] += cx * w2;
+                acc[RQ_Y] += cy * w2;
+                acc[RQ_Z] += cz * w2;
+                acc[RQ_R2] += (cx * cx + cy * cy + cz * cz) * w2;
+            }
+        }
+    }
+    block_sums<NQR, NTP>(acc, L.part_rows + ((size_t)i * L.nb_rows + blockIdx.x) * NQR, red);
+}
+
+// ---------------------------------------------------------------------------
+// Reflection projection of u_i in place: u <- (u + sign u o R)/2, R reflecting
+// the axes in `axes`; `which` = 1 projects the freshly updated arrays of a step,
+// 0 the current ones.  One workgroup per plane x and job; the plane is paired
+// with its mirror plane (the workgroup of the larger index exits), each site
+// pair {s, R s} is handled by one thread.  Partial sums of |P u|^2 per plane.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(NT) k_project(const JobRef *__restrict__ jobs, int force_sign,
+                                                int force_axes, int which) {
+    __shared__ double red[NT / 64];
+    const JobRef job = jobs[blockIdx.y];
+    const LatDev &L = *job.lat;
+    const int i = job.state;
+    const int sign = force_sign ? force_sign : L.psign[i];
+    const int axes = force_sign ? force_axes : L.paxes[i];
+    const int n = L.n, center = L.center;
+    const int x = blockIdx.x;
+    const int xm = (axes & 1) ? mirror_idx(x, n, center) : x;
+    double acc[1] = {0.0};
+    double *dst = L.part_proj + (size_t)i * L.nb_proj + x;
+    if (sign == 0) return;  // uniform over the workgroup
+    if (xm < x) {
+        if (threadIdx.x == 0) *dst = 0.0;
+        return;
+    }
+    R *u = (R *)state_buf(L, L.step, which, i);
+    const size_t n2 = (size_t)n * n;
+    R *pa_ = u + (size_t)x * n2;
+    R *pb_ = u + (size_t)xm * n2;
+    const R sg = (R)sign;
+    for (int e = threadIdx.x; e < (int)n2; e += NT) {
+        const int y = e / n, z = e % n;
+        const int ym = (axes & 2) ? mirror_idx(y, n, center) : y;
+        const int zm = (axes & 4) ? mirror_idx(z, n, center) : z;
+        const int m = ym * n + zm;
+        if (xm == x && m < e) continue;
+        if (xm == x && m == e) {
+            const R val = sign > 0 ? pa_[e] : (R)0;
+            pa_[e] = val;
+            acc[0] += (double)val * (double)val;
+        } else {
+            const R a = pa_[e], b = pb_[m];
+            const R pa = (R)0.5 * (a + sg * b);
+            pa_[e] = pa;
+            pb_[m] = sg * pa;
+            acc[0] += 2.0 * (double)pa * (double)pa;
+        }
+    }
+    block_sums<1, NT>(acc, dst, red);
+}
+
+// ---------------------------------------------------------------------------
+// Gram sums <u_j|u_l>, j <= l < K, one lattice per blockIdx.y; KM >= K is the
+// compile-time bound.  Each workgroup sums a fixed contiguous range of sites.
+// Runs on steps that orthogonalise (or when forced); `which` as for k_project.
+// ---------------------------------------------------------------------------
+template <typename R, int KM>
+__global__ void __launch_bounds__(NT) k_gram(const JobRef *__restrict__ lats, int force, int which) {
+    constexpr int NG = MAXK * (MAXK + 1) / 2;
+    constexpr int NGK = KM * (KM + 1) / 2;
+    __shared__ double red[NGK * (NT / 64)];
+    const LatDev &L = *lats[blockIdx.y].lat;
+    const int K = L.nstates;
+    if (K < 2 || K > KM) return;
+    if (!force && (L.ortho_every <= 0 || ((L.step + 1) % L.ortho_every) != 0)) return;
+    const int n = L.n;
+    const size_t n3 = (size_t)n * n * n;
+    const size_t per = (n3 + gridDim.x - 1) / gridDim.x;
+    const size_t s0 = (size_t)blockIdx.x * per, s1 = s0 + per < n3 ? s0 + per : n3;
+    const R *uu[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) uu[j] = (const R *)state_buf(L, L.step, which, j < K ? j : 0);
+    double acc[NGK];
+#pragma unroll
+    for (int g = 0; g < NGK; ++g) acc[g] = 0.0;
+    for (size_t s = s0 + threadIdx.x; s < s1; s += NT) {
+        double val[KM];
+#pragma unroll
+        for (int j = 0; j < KM; ++j) val[j] = j < K ? (double)uu[j][s] : 0.0;
+        int g = 0;
+#pragma unroll
+        for (int l = 0; l < KM; ++l)
+#pragma unroll
+            for (int j = 0; j <= l; ++j) acc[g++] += val[j] * val[l];
+    }
+    // slot layout l (l + 1) / 2 + j, the same for every KM
+    block_sums<NGK, NT>(acc, L.part_gram + (size_t)blockIdx.x * NG, red);
+}
+
+// out_i = sum_j coef[j][i] u_j (materialise the current state i), FP64 combination.
+template <typename R>
+__global__ void __launch_bounds__(NT) k_combine(const JobRef *__restrict__ jobs, void *const *outs) {
+    const JobRef job = jobs[blockIdx.y];
+    const LatDev &L = *job.lat;
+    LatView<R> vw;
+    load_view(vw, L, job.state);
+    const int n = L.n;
+    const size_t n3 = (size_t)n * n * n;
+    R *out = (R *)outs[blockIdx.y];
+    for (size_t s = (size_t)blockIdx.x * NT + threadIdx.x; s < n3; s += (size_t)gridDim.x * NT)
+        out[s] = lazy_psi(vw, s);
+}
+
+template <typename S, typename D>
+__global__ void __launch_bounds__(NT) k_convert(const S *__restrict__ src, D *__restrict__ dst, size_t count) {
+    const size_t stride = (size_t)gridDim.x * NT;
+    for (size_t s = (size_t)blockIdx.x * NT + threadIdx.x; s < count; s += stride) dst[s] = (D)src[s];
+}
+
+}  // namespace itse

@@ -18,6 +18,7 @@ struct Group {
     int njobs = 0;
     const JobRef *lats = nullptr;  // device array of (lattice, 0)
     int nlats = 0;
+    int kmax = 1;                  // largest number of states among the lattices
 };
 
 itse_status fail(itse_status st, const char *fmt, ...);
@@ -45,7 +46,6 @@ struct itse_lattice {
     itse::LatDev *dev = nullptr;    // device record
     itse::JobRef *jobs_dev = nullptr;  // [MAXK] (lattice, state i)
     itse::JobRef *lat_dev = nullptr;   // [1] (lattice, 0)
-    void **phi_ptrs_dev = nullptr;     // [MAXK] phi buffers (materialisation targets)
     void **tmp_ptrs_dev = nullptr;     // [MAXK] all pointing at tmp
     void *tmp = nullptr;               // N^3 scratch in the lattice precision
     void *staging = nullptr;
@@ -58,6 +58,7 @@ struct itse_lattice {
     hipGraphExec_t graph1 = nullptr;
     hipGraphExec_t graphN = nullptr;
     itse_lattice *shadow = nullptr;    // FP64 twin for polish
+    void *cur_raw(int i) const { return itse::state_buf(host, steps_host, 0, i); }
     void *stage_buf(size_t bytes);
     ~itse_lattice();
 };

@@ -54,24 +54,21 @@ extern "C" const char *itse_version(void) { return "itse 0.1 (gfx950)"; }
 // ------------------------------------------------------------------------------------
 namespace itse {
 
-__device__ double fixed_sum(const double *p, int count, int stride, double *red) {
-    const int tid = threadIdx.x;
+constexpr int FIN_NT = 1024;
+
+// Fixed-order sum of count values p[b * stride] by the 16 lanes of a lane group:
+// lane l takes b = l, l + 16, ...; the 16 partial sums are combined by a fixed
+// butterfly.  Every lane of the group returns the total.
+__device__ __forceinline__ double group16_sum(const double *p, int count, int stride, int sub) {
     double acc = 0.0;
-    for (int b = tid; b < count; b += NT) acc += p[(size_t)b * stride];
-    red[tid] = acc;
-    __syncthreads();
-    for (int s = NT / 2; s > 0; s >>= 1) {
-        if (tid < s) red[tid] += red[tid + s];
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
+    for (int b = sub; b < count; b += 16) acc += p[(size_t)b * stride];
+#pragma unroll
+    for (int m = 8; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 16);
+    return acc;
 }
 
-__global__ void __launch_bounds__(NT) k_finalize(const JobRef *__restrict__ lats, int mode) {
+__global__ void __launch_bounds__(FIN_NT) k_finalize(const JobRef *__restrict__ lats, int mode) {
     constexpr int NG = MAXK * (MAXK + 1) / 2;
-    __shared__ double red[NT];
     __shared__ double rows[MAXK][NQR];
     __shared__ double cols[MAXK][NQC];
     __shared__ double proj[MAXK];
@@ -80,30 +77,44 @@ __global__ void __launch_bounds__(NT) k_finalize(const JobRef *__restrict__ lats
     const int K = L.nstates;
     const bool ortho_step = (mode == FIN_STEP) && K > 1 && L.ortho_every > 0 &&
                             ((L.step + 1) % L.ortho_every) == 0;
-    for (int i = 0; i < K; ++i) {
-        for (int q = 0; q < NQR; ++q) {
-            const double s = fixed_sum(L.part_rows + (size_t)i * L.nb_rows * NQR + q, L.nb_rows, NQR, red);
-            if (threadIdx.x == 0) rows[i][q] = s;
+    // quantities: K*NQR row sums, K*NQC column sums (moments), K projection norms, Gram entries
+    const int q_rows = K * NQR;
+    const int q_cols = L.moments ? K * NQC : 0;
+    const int q_proj = mode == FIN_STEP ? K : 0;
+    const int q_gram = ortho_step ? K * (K + 1) / 2 : 0;
+    const int total = q_rows + q_cols + q_proj + q_gram;
+    const int grp = threadIdx.x >> 4, sub = threadIdx.x & 15;
+    for (int q = grp; q < total; q += FIN_NT / 16) {
+        const double *p;
+        int count, stride;
+        double *dst;
+        if (q < q_rows) {
+            const int i = q / NQR, c = q % NQR;
+            p = L.part_rows + (size_t)i * L.nb_rows * NQR + c;
+            count = L.nb_rows;
+            stride = NQR;
+            dst = &rows[i][c];
+        } else if (q < q_rows + q_cols) {
+            const int t = q - q_rows, i = t / NQC, c = t % NQC;
+            p = L.part_cols + (size_t)i * L.nb_cols * NQC + c;
+            count = L.nb_cols;
+            stride = NQC;
+            dst = &cols[i][c];
+        } else if (q < q_rows + q_cols + q_proj) {
+            const int i = q - q_rows - q_cols;
+            p = L.part_proj + (size_t)i * L.nb_proj;
+            count = L.psign[i] != 0 ? L.nb_proj : 0;  // no partials without a projection
+            stride = 1;
+            dst = &proj[i];
+        } else {
+            const int slot = q - q_rows - q_cols - q_proj;  // l (l + 1) / 2 + j
+            p = L.part_gram + slot;
+            count = L.nb_gram;
+            stride = NG;
+            dst = &gram[slot];
         }
-        if (L.moments) {
-            for (int q = 0; q < NQC; ++q) {
-                const double s = fixed_sum(L.part_cols + (size_t)i * L.nb_cols * NQC + q, L.nb_cols, NQC, red);
-                if (threadIdx.x == 0) cols[i][q] = s;
-            }
-        }
-        if (mode == FIN_STEP && L.psign[i] != 0) {
-            const double s = fixed_sum(L.part_proj + (size_t)i * L.nb_proj, L.nb_proj, 1, red);
-            if (threadIdx.x == 0) proj[i] = s;
-        }
-    }
-    if (ortho_step) {
-        for (int l = 0, g = 0; l < K; ++l)
-            for (int j = 0; j <= l; ++j, ++g) {
-                const int slot = l * (l + 1) / 2 + j;
-                const double s = fixed_sum(L.part_gram + slot, L.nb_gram, NG, red);
-                if (threadIdx.x == 0) gram[slot] = s;
-                (void)g;
-            }
+        const double s = group16_sum(p, count, stride, sub);
+        if (sub == 0) *dst = s;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
@@ -208,7 +219,7 @@ __global__ void __launch_bounds__(NT) k_check_potential(const LatDev *lp) {
 
 hipError_t launch_finalize(const JobRef *lats, int nlats, int mode, hipStream_t s) {
     if (nlats <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finalize, dim3(nlats), dim3(NT), 0, s, lats, mode);
+    hipLaunchKernelGGL(k_finalize, dim3(nlats), dim3(FIN_NT), 0, s, lats, mode);
     return hipGetLastError();
 }
 
@@ -308,19 +319,17 @@ static itse_status twiddles(int n, int prec, void **out) {
 template <typename R>
 static hipError_t seq_forward_kin(const Group &g, int inv_mode, hipStream_t s) {
     hipError_t e;
-    if ((e = Launch<R>::rows_fwd(g.n, g.variant, g.jobs, g.njobs, s)) != hipSuccess) return e;
-    if ((e = Launch<R>::cols(g.n, g.variant, COL_FWD, 1, 0, g.jobs, g.njobs, s)) != hipSuccess) return e;
-    if ((e = Launch<R>::cols(g.n, g.variant, COL_KIN, 0, 1, g.jobs, g.njobs, s)) != hipSuccess) return e;
-    if ((e = Launch<R>::cols(g.n, g.variant, COL_INV, 1, 0, g.jobs, g.njobs, s)) != hipSuccess) return e;
-    return Launch<R>::rows_inv(g.n, g.variant, inv_mode, g.jobs, g.njobs, s);
+    if ((e = Launch<R>::plane_fwd(g.n, g.variant, g.jobs, g.njobs, s)) != hipSuccess) return e;
+    if ((e = Launch<R>::columns(g.n, g.variant, COL_KIN, 1, g.jobs, g.njobs, nullptr, s)) != hipSuccess) return e;
+    return Launch<R>::plane_inv(g.n, g.variant, inv_mode, g.jobs, g.njobs, s);
 }
 
 template <typename R>
 static hipError_t seq_step(const Group &g, hipStream_t s) {
     hipError_t e;
     if ((e = seq_forward_kin<R>(g, INV_UPDATE, s)) != hipSuccess) return e;
-    if ((e = Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, s)) != hipSuccess) return e;
-    if ((e = Launch<R>::gram(g.n, g.lats, g.nlats, 0, s)) != hipSuccess) return e;
+    if ((e = Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, 1, s)) != hipSuccess) return e;
+    if ((e = Launch<R>::gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s)) != hipSuccess) return e;
     return launch_finalize(g.lats, g.nlats, FIN_STEP, s);
 }
 
@@ -343,6 +352,9 @@ hipError_t enqueue_eval(const Group &g, hipStream_t s) {
 itse_lattice::~itse_lattice() {}
 
 namespace itse {
+
+// Current raw array of state i on the device (the device flips buffers every step).
+static void *cur_state(itse_lattice *L, int i) { return L->cur_raw(i); }
 
 void *lat_alloc(itse_lattice *L, size_t bytes) {
     void *p = nullptr;
@@ -413,6 +425,7 @@ Group single_group(itse_lattice *L) {
     g.njobs = L->d.nstates;
     g.lats = L->lat_dev;
     g.nlats = 1;
+    g.kmax = L->d.nstates;
     return g;
 }
 
@@ -423,17 +436,19 @@ Group state_group(itse_lattice *L, int i) {
     return g;
 }
 
-// Replace the lazy representation by materialised states: phi_i = sum_j coef[j][i] u_j,
-// copy phi -> u, coef = identity.
+// Replace the lazy representation by materialised states: psi_i = sum_(j<=i) coef[j][i] u_j
+// is formed in the scratch array and copied over u_i, highest state first (psi_i only
+// reads u_0..u_i), then coef = identity.
 itse_status materialise(itse_lattice *L) {
     const int K = L->d.nstates;
     const size_t bytes = (size_t)L->d.n * L->d.n * L->d.n * real_bytes(L->d.precision);
-    hipError_t e = L->d.precision == ITSE_FP32
-                       ? Launch<float>::combine(L->d.n, L->jobs_dev, K, L->phi_ptrs_dev, L->stream)
-                       : Launch<double>::combine(L->d.n, L->jobs_dev, K, L->phi_ptrs_dev, L->stream);
-    if (e != hipSuccess) return fail(ITSE_EDEVICE, "combine launch: %s", hipGetErrorString(e));
-    for (int i = 0; i < K; ++i)
-        HIPCHK(hipMemcpyAsync(L->host.u[i], L->host.phi[i], bytes, hipMemcpyDeviceToDevice, L->stream));
+    for (int i = K - 1; i >= 0; --i) {
+        hipError_t e = L->d.precision == ITSE_FP32
+                           ? Launch<float>::combine(L->d.n, L->jobs_dev + i, 1, L->tmp_ptrs_dev, L->stream)
+                           : Launch<double>::combine(L->d.n, L->jobs_dev + i, 1, L->tmp_ptrs_dev, L->stream);
+        if (e != hipSuccess) return fail(ITSE_EDEVICE, "combine launch: %s", hipGetErrorString(e));
+        HIPCHK(hipMemcpyAsync(cur_state(L, i), L->tmp, bytes, hipMemcpyDeviceToDevice, L->stream));
+    }
     return set_identity_coef(L);
 }
 
@@ -445,15 +460,24 @@ extern "C" size_t itse_footprint_bytes(const itse_desc *d) {
     const size_t n = (size_t)d->n, n3 = n * n * n;
     const size_t K = (size_t)std::max(1, std::min(d->nstates, MAXK));
     const size_t spec = n * n * (n / 2 + 1) * 2 * w;
-    Sched s = prec_supported(d->n, d->precision) ? prec_schedule(d->n, d->precision, 0) : Sched{};
-    const size_t arena = (size_t)MAXK * ((size_t)s.nb_rows * NQR + (size_t)s.nb_cols * NQC + s.nb_proj) * 8 +
-                         (size_t)s.nb_gram * (MAXK * (MAXK + 1) / 2) * 8;
+    size_t arena = 0;
+    if (prec_supported(d->n, d->precision)) {
+        const int nv = d->precision == ITSE_FP32 ? Launch<float>::variants(d->n) : Launch<double>::variants(d->n);
+        for (int v = 0; v < nv; ++v) {
+            const Sched s = prec_schedule(d->n, d->precision, v);
+            const size_t a = (size_t)MAXK * ((size_t)s.nb_rows * NQR + (size_t)s.nb_cols * NQC + s.nb_proj) * 8 +
+                             (size_t)s.nb_gram * (MAXK * (MAXK + 1) / 2) * 8;
+            arena = std::max(arena, a);
+        }
+    }
     const size_t hist = (size_t)HIST_CAP * MAXK * sizeof(ObsDev);
-    return K * (2 * n3 * w + spec) + n3 * w + n3 * w /*temp*/ + arena + hist + sizeof(LatDev) + 4096 + n * 8;
+    // per state: two raw arrays u_i (current, next) and the half spectrum; shared: potential, scratch array,
+    // staging for a host upload in the other precision (n^3 doubles), partial sums, history
+    return K * (2 * n3 * w + spec) + n3 * w + n3 * w + n3 * 8 + arena + hist + sizeof(LatDev) + 8192 + n * 8;
 }
 
 static bool valid_n(int n) {
-    if (n < 8 || n > 512) return false;
+    if (n < 8 || n > 256) return false;
     int m = n;
     while (m % 2 == 0) m /= 2;
     while (m % 3 == 0) m /= 3;
@@ -464,7 +488,7 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
                                    void *alloc_user, itse_lattice **out) {
     if (!d || !out) return fail(ITSE_EINVAL, "null argument");
     *out = nullptr;
-    if (!valid_n(d->n)) return fail(ITSE_EINVAL, "n = %d: need 8 <= n <= 512 with prime factors 2 and 3", d->n);
+    if (!valid_n(d->n)) return fail(ITSE_EINVAL, "n = %d: need 8 <= n <= 256 with prime factors 2 and 3", d->n);
     if (!(d->a > 0) || !(d->mass > 0) || !(d->dtau > 0) || !std::isfinite(d->a) || !std::isfinite(d->mass) ||
         !std::isfinite(d->dtau))
         return fail(ITSE_EINVAL, "a, mass and dtau must be finite and > 0");
@@ -508,10 +532,10 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
     H.dtau = d->dtau;
     H.h = 0.5 * d->dtau;
     for (int i = 0; i < K; ++i) {
-        H.u[i] = lat_alloc(L, n3 * w);
-        H.phi[i] = lat_alloc(L, n3 * w);
+        H.ub[0][i] = lat_alloc(L, n3 * w);
+        H.ub[1][i] = lat_alloc(L, n3 * w);
         H.spec[i] = lat_alloc(L, spec);
-        if (!H.u[i] || !H.phi[i] || !H.spec[i]) return cleanup(fail(ITSE_ENOMEM, "state buffers (%zu bytes)", n3 * w));
+        if (!H.ub[0][i] || !H.ub[1][i] || !H.spec[i]) return cleanup(fail(ITSE_ENOMEM, "state buffers (%zu bytes)", n3 * w));
     }
     H.v = lat_alloc(L, n3 * w);
     L->tmp = lat_alloc(L, n3 * w);
@@ -528,10 +552,9 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
     L->dev = (LatDev *)lat_alloc(L, sizeof(LatDev));
     L->jobs_dev = (JobRef *)lat_alloc(L, sizeof(JobRef) * MAXK);
     L->lat_dev = (JobRef *)lat_alloc(L, sizeof(JobRef));
-    L->phi_ptrs_dev = (void **)lat_alloc(L, sizeof(void *) * MAXK);
     L->tmp_ptrs_dev = (void **)lat_alloc(L, sizeof(void *) * MAXK);
     if (!H.v || !L->tmp || !H.part_rows || !H.part_cols || !H.part_proj || !H.part_gram || !H.hist || !ktab ||
-        !L->dev || !L->jobs_dev || !L->lat_dev || !L->phi_ptrs_dev || !L->tmp_ptrs_dev)
+        !L->dev || !L->jobs_dev || !L->lat_dev || !L->tmp_ptrs_dev)
         return cleanup(fail(ITSE_ENOMEM, "lattice buffers"));
     H.ktab = ktab;
     void *tw = nullptr;
@@ -558,12 +581,11 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
     std::vector<double> tab;
     kinetic_axis_table(*d, tab);
     std::vector<JobRef> jobs(MAXK);
-    std::vector<void *> phis(MAXK, nullptr), tmps(MAXK, nullptr);
+    std::vector<void *> tmps(MAXK, nullptr);
     for (int i = 0; i < MAXK; ++i) {
         jobs[i].lat = L->dev;
         jobs[i].state = i;
         jobs[i].pad_ = 0;
-        phis[i] = H.phi[i];
         tmps[i] = L->tmp;
     }
     JobRef lj{L->dev, 0, 0};
@@ -576,11 +598,10 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
     CK(hipMemcpyAsync(ktab, tab.data(), n * 8, hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(L->jobs_dev, jobs.data(), sizeof(JobRef) * MAXK, hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(L->lat_dev, &lj, sizeof(JobRef), hipMemcpyHostToDevice, s));
-    CK(hipMemcpyAsync(L->phi_ptrs_dev, phis.data(), sizeof(void *) * MAXK, hipMemcpyHostToDevice, s));
     CK(hipMemcpyAsync(L->tmp_ptrs_dev, tmps.data(), sizeof(void *) * MAXK, hipMemcpyHostToDevice, s));
     for (int i = 0; i < K; ++i) {
-        CK(hipMemsetAsync(H.u[i], 0, n3 * w, s));
-        CK(hipMemsetAsync(H.phi[i], 0, n3 * w, s));
+        CK(hipMemsetAsync(H.ub[0][i], 0, n3 * w, s));
+        CK(hipMemsetAsync(H.ub[1][i], 0, n3 * w, s));
     }
     CK(hipMemsetAsync(H.v, 0, n3 * w, s));
     CK(hipMemsetAsync(H.hist, 0, (size_t)HIST_CAP * MAXK * sizeof(ObsDev), s));
@@ -626,7 +647,6 @@ static itse_status copy_in(itse_lattice *L, const void *src, int dtype, int on_d
     const void *dsrc = src;
     void *staging = nullptr;
     if (!on_device) {
-        // stage in the phi buffer of the last state is unsafe; use a dedicated buffer
         staging = L->stage_buf(n3 * sw);
         if (!staging) return fail(ITSE_ENOMEM, "staging buffer");
         HIPCHK(hipMemcpyAsync(staging, src, n3 * sw, hipMemcpyHostToDevice, L->stream));
@@ -676,7 +696,7 @@ extern "C" itse_status itse_set_state(itse_lattice *L, int i, const void *psi, i
     if (dtype != ITSE_DTYPE_F32 && dtype != ITSE_DTYPE_F64) return fail(ITSE_EINVAL, "dtype");
     itse_status st = materialise(L);
     if (st) return st;
-    return copy_in(L, psi, dtype, on_device, L->host.u[i]);
+    return copy_in(L, psi, dtype, on_device, cur_state(L, i));
 }
 
 extern "C" itse_status itse_get_state(itse_lattice *L, int i, void *out, int dtype, int on_device) {
@@ -870,13 +890,13 @@ static double host_fixed_sum(const std::vector<double> &p, int count, int stride
 
 static itse_status gram_host(itse_lattice *L, double G[MAXK][MAXK]) {
     constexpr int NG = MAXK * (MAXK + 1) / 2;
-    hipError_t e = L->d.precision == ITSE_FP32 ? Launch<float>::gram(L->d.n, L->lat_dev, 1, 1, L->stream)
-                                               : Launch<double>::gram(L->d.n, L->lat_dev, 1, 1, L->stream);
+    const int K = L->d.nstates;
+    hipError_t e = L->d.precision == ITSE_FP32 ? Launch<float>::gram(L->d.n, K, L->lat_dev, 1, 1, 0, L->stream)
+                                               : Launch<double>::gram(L->d.n, K, L->lat_dev, 1, 1, 0, L->stream);
     if (e != hipSuccess) return fail(ITSE_EDEVICE, "gram: %s", hipGetErrorString(e));
     std::vector<double> part((size_t)L->host.nb_gram * NG);
     HIPCHK(hipMemcpyAsync(part.data(), L->host.part_gram, part.size() * 8, hipMemcpyDeviceToHost, L->stream));
     HIPCHK(hipStreamSynchronize(L->stream));
-    const int K = L->d.nstates;
     for (int l = 0; l < K; ++l)
         for (int j = 0; j <= l; ++j) {
             const double s = host_fixed_sum(part, L->host.nb_gram, NG, l * (l + 1) / 2 + j);
@@ -954,8 +974,8 @@ extern "C" itse_status itse_project_parity(itse_lattice *L, int i, int sign, int
     st = norm_host(L, i, &before);
     if (st) return st;
     hipError_t e = L->d.precision == ITSE_FP32
-                       ? Launch<float>::project(L->d.n, L->jobs_dev + i, 1, sign, axes, L->stream)
-                       : Launch<double>::project(L->d.n, L->jobs_dev + i, 1, sign, axes, L->stream);
+                       ? Launch<float>::project(L->d.n, L->jobs_dev + i, 1, sign, axes, 0, L->stream)
+                       : Launch<double>::project(L->d.n, L->jobs_dev + i, 1, sign, axes, 0, L->stream);
     if (e != hipSuccess) return fail(ITSE_EDEVICE, "project: %s", hipGetErrorString(e));
     std::vector<double> part(L->host.nb_proj);
     HIPCHK(hipMemcpyAsync(part.data(), L->host.part_proj + (size_t)i * L->host.nb_proj, part.size() * 8,
@@ -987,18 +1007,13 @@ extern "C" itse_status itse_spectrum(itse_lattice *L, int i, void *out) {
     Group g = state_group(L, i);
     hipError_t e;
     if (L->d.precision == ITSE_FP32) {
-        e = Launch<float>::rows_fwd(g.n, g.variant, g.jobs, 1, L->stream);
-        if (e == hipSuccess) e = Launch<float>::cols(g.n, g.variant, COL_FWD, 1, 0, g.jobs, 1, L->stream);
-        if (e == hipSuccess) e = Launch<float>::cols(g.n, g.variant, COL_FWD, 0, 0, g.jobs, 1, L->stream);
+        e = Launch<float>::plane_fwd(g.n, g.variant, g.jobs, 1, L->stream);
+        if (e == hipSuccess) e = Launch<float>::columns(g.n, g.variant, COL_FWD, 0, g.jobs, 1, out, L->stream);
     } else {
-        e = Launch<double>::rows_fwd(g.n, g.variant, g.jobs, 1, L->stream);
-        if (e == hipSuccess) e = Launch<double>::cols(g.n, g.variant, COL_FWD, 1, 0, g.jobs, 1, L->stream);
-        if (e == hipSuccess) e = Launch<double>::cols(g.n, g.variant, COL_FWD, 0, 0, g.jobs, 1, L->stream);
+        e = Launch<double>::plane_fwd(g.n, g.variant, g.jobs, 1, L->stream);
+        if (e == hipSuccess) e = Launch<double>::columns(g.n, g.variant, COL_FWD, 0, g.jobs, 1, out, L->stream);
     }
     if (e != hipSuccess) return fail(ITSE_EDEVICE, "spectrum launch: %s", hipGetErrorString(e));
-    const size_t n = L->d.n;
-    const size_t bytes = n * n * (n / 2 + 1) * 2 * real_bytes(L->d.precision);
-    HIPCHK(hipMemcpyAsync(out, L->host.spec[i], bytes, hipMemcpyDeviceToDevice, L->stream));
     return ITSE_OK;
 }
 
@@ -1038,19 +1053,16 @@ namespace itse {
 template <typename R>
 static hipError_t launch_pass(const Group &g, int p, hipStream_t s) {
     switch (p) {
-    case 0: return Launch<R>::rows_fwd(g.n, g.variant, g.jobs, g.njobs, s);
-    case 1: return Launch<R>::cols(g.n, g.variant, COL_FWD, 1, 0, g.jobs, g.njobs, s);
-    case 2: return Launch<R>::cols(g.n, g.variant, COL_KIN, 0, 1, g.jobs, g.njobs, s);
-    case 3: return Launch<R>::cols(g.n, g.variant, COL_INV, 1, 0, g.jobs, g.njobs, s);
-    case 4: return Launch<R>::rows_inv(g.n, g.variant, INV_UPDATE, g.jobs, g.njobs, s);
-    case 5: return Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, s);
-    case 6: return Launch<R>::gram(g.n, g.lats, g.nlats, 0, s);
+    case 0: return Launch<R>::plane_fwd(g.n, g.variant, g.jobs, g.njobs, s);
+    case 1: return Launch<R>::columns(g.n, g.variant, COL_KIN, 1, g.jobs, g.njobs, nullptr, s);
+    case 2: return Launch<R>::plane_inv(g.n, g.variant, INV_UPDATE, g.jobs, g.njobs, s);
+    case 3: return Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, 1, s);
+    case 4: return Launch<R>::gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s);
     default: return launch_finalize(g.lats, g.nlats, FIN_STEP, s);
     }
 }
-static const char *pass_names[] = {"k_rows_fwd", "k_cols<COL_FWD>", "k_cols<COL_KIN>", "k_cols<COL_INV>",
-                                   "k_rows_inv", "k_project", "k_gram", "k_finalize"};
-constexpr int NPASS = 8;
+static const char *pass_names[] = {"k_plane_fwd", "k_columns", "k_plane_inv", "k_project", "k_gram", "k_finalize"};
+constexpr int NPASS = 6;
 }  // namespace itse
 
 extern "C" itse_status itse_profile_step(itse_lattice *L, int nsteps, double *ms_out, int *npass, char *names,

@@ -281,3 +281,13 @@ def schedule(n: int, precision: str = "fp32") -> str:
     buf = ctypes.create_string_buffer(1024)
     check(L.itse_schedule_get(int(n), _PREC[precision], buf, 1024))
     return buf.value.decode()
+
+
+def set_schedule(n: int, precision: str, variant: int):
+    """Select the transform schedule variant used by lattices created afterwards."""
+    check(_lib.load().itse_schedule_set(int(n), _PREC[precision], int(variant)))
+
+
+def schedule_variants(n: int, precision: str = "fp32") -> int:
+    import json
+    return int(json.loads(schedule(n, precision))["variants"])

@@ -1,0 +1,132 @@
+"""GPU parity of the three-pass step at the larger lattice sizes and for every
+schedule variant (split factor of the y axis, workgroup shapes), through the C ABI,
+against the FP64 oracle.
+
+Tolerances: FP64 lattices 1e-12 (max-abs / max) for one transform or kinetic
+application and 1e-10 relative for energies along trajectories.  FP32 lattices:
+one transform rounds to ~eps32 * log2(N) relative (6e-8 * 8 at N = 256); the
+bound used is 2e-5 of the largest value, and 1e-5 relative on step energies.
+"""
+import json
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+CASES = [(48, "fp64", 0), (96, "fp64", 0), (128, "fp32", 0), (128, "fp32", 1), (128, "fp64", 0),
+         (192, "fp32", 0), (192, "fp64", 0), (256, "fp32", 0), (256, "fp32", 1), (256, "fp64", 0),
+         (256, "fp64", 1)]
+
+
+def _tol(prec):
+    return 1e-12 if prec == "fp64" else 2e-5
+
+
+def _rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def _lat(itse, n, prec, variant, kin=3, nstates=1, center="origin", a=None, mass=1.3):
+    itse.set_schedule(n, prec, variant)
+    a = 6.4 / n if a is None else a
+    dtau = a * a * mass / 8 if kin in (1, 2) else a / 4
+    return itse.Lattice(n, a, mass, dtau, kin=kin, subtract_rest_mass=True, precision=prec,
+                        center=center, nstates=nstates)
+
+
+@pytest.fixture(autouse=True)
+def _reset_schedules(itse):
+    yield
+    for n, prec, _ in CASES:
+        itse.set_schedule(n, prec, 0)
+
+
+def _olat(orc, lat):
+    d = lat.desc
+    return orc.lattice(d.n, d.a, d.mass, d.dtau, d.kin, bool(d.subtract_rest_mass),
+                       "cell" if d.center == 0 else "origin")
+
+
+@pytest.mark.parametrize("n,prec,variant", CASES)
+def test_spectrum_schedules(itse, orc, n, prec, variant):
+    lat = _lat(itse, n, prec, variant)
+    assert json.loads(itse.schedule(n, prec))["variant"] == variant
+    dt = np.float32 if prec == "fp32" else np.float64
+    psi = synth.random_state(n, 300 + n + variant, dtype=dt)
+    lat.set_state(0, psi)
+    spec = lat.spectrum(0).cpu().numpy().astype(np.float64)
+    got = spec[..., 0] + 1j * spec[..., 1]
+    ref = orc.fft3d(psi.astype(np.float64), -1)[:, :, : n // 2 + 1]
+    assert _rel(got, ref) < _tol(prec)
+    lat.close()
+
+
+@pytest.mark.parametrize("n,prec,variant", CASES)
+@pytest.mark.parametrize("kin", [1, 3])
+def test_kinetic_schedules(itse, orc, n, prec, variant, kin):
+    lat = _lat(itse, n, prec, variant, kin=kin)
+    dt = np.float32 if prec == "fp32" else np.float64
+    psi = synth.random_state(n, 500 + n + kin, dtype=dt)
+    lat.set_state(0, psi)
+    got = lat.apply_kinetic(0).cpu().numpy().astype(np.float64)
+    ref = orc.apply_kinetic(_olat(orc, lat), psi.astype(np.float64))
+    assert _rel(got, ref) < _tol(prec)
+    lat.close()
+
+
+@pytest.mark.parametrize("n,prec,variant", [(96, "fp64", 0), (128, "fp64", 0), (128, "fp32", 1),
+                                            (192, "fp32", 0)])
+def test_multistate_steps_large(itse, orc, n, prec, variant):
+    """Three states (even, odd, odd deflated against the odd one), Cornell potential,
+    a few steps: every step's energies and the final states match the oracle."""
+    steps = 4
+    a = 6.4 / n
+    lat = _lat(itse, n, prec, variant, kin=3, nstates=3, a=a)
+    dt = np.float32 if prec == "fp32" else np.float64
+    v = synth.potential_cornell(n, a, "origin", sigma=0.2, alpha=0.4, aniso=0.05).astype(dt)
+    states = synth.random_states(n, 3, seed=40, dtype=dt)
+    lat.set_potential(v)
+    for i, s in enumerate(states):
+        lat.set_state(i, s)
+    lat.set_options(ortho_every=1, moments=True, parity=(1, -1, -1))
+    lat.step(steps)
+    hist = lat.history(steps)
+    ostates, ohist = orc.step(_olat(orc, lat), [s.astype(np.float64) for s in states],
+                              v.astype(np.float64), steps, parity=(1, -1, -1))
+    etol = 1e-10 if prec == "fp64" else 1e-5
+    for s in range(steps):
+        for i in range(3):
+            for f in ("energy", "norm2", "x", "r2", "parity_even"):
+                g, r = hist[s][i][f], ohist[s][i][f]
+                assert abs(g - r) <= etol * max(1.0, abs(r)), (s, i, f, g, r)
+    stol = 1e-10 if prec == "fp64" else 1e-4
+    for i in range(3):
+        assert _rel(lat.get_state(i), ostates[i]) < stol
+    lat.close()
+
+
+def test_precision_workload_first_steps(itse, orc):
+    """The 256^3 FP32 workload the benchmark times, in its default schedule: the
+    energies of the first steps match the FP64 oracle on the same FP32 inputs."""
+    p = synth.config_precision(256)
+    v = p.potential_array(np.float64).astype(np.float32)
+    states = [s.astype(np.float32) for s in p.initial_states()]
+    lat = itse.Lattice(p.n, p.a, p.mass, p.dtau, kin=p.kin, subtract_rest_mass=True,
+                       precision="fp32", center=p.center, nstates=p.nstates)
+    lat.set_potential(v)
+    for i, s in enumerate(states):
+        lat.set_state(i, s)
+    lat.set_options(ortho_every=1, moments=False, parity=list(p.parity))
+    steps = 2
+    lat.step(steps)
+    hist = lat.history(steps)
+    _, ohist = orc.step(_olat(orc, lat), [s.astype(np.float64) for s in states],
+                        v.astype(np.float64), steps, parity=list(p.parity), record=True)
+    for s in range(steps):
+        for i in range(p.nstates):
+            g, r = hist[s][i]["energy"], ohist[s][i]["energy"]
+            assert abs(g - r) <= 1e-5 * abs(r), (s, i, g, r)
+    lat.close()
