@@ -29,20 +29,26 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 
 
-def pass_bytes(n: int, w: int, nstates: int, parity, ortho: bool):
+def pass_bytes(n: int, w: int, nstates: int, parity, ortho: bool, axes=None):
     """Algorithmic bytes of each kernel of one step (all states): what each kernel
     must read and write once.  States are kept as psi_i = sum_(j<=i) c_ji u_j, so
-    the two plane passes read i+1 arrays for state i when Gram-Schmidt is on."""
+    the two plane passes read i+1 arrays for state i when Gram-Schmidt is on.  When
+    all projected states reflect the same axes, the projection shares one pass with
+    the Gram sums (k_project_gram); otherwise k_project projects each state alone."""
     sites = n ** 3
     s = 2.0 * w * (n // 2 + 1) / n        # half-spectrum bytes per lattice site
     k = nstates
     reads = sum((i + 1) if ortho else 1 for i in range(k))
+    proj = [i for i in range(k) if parity and parity[i]]
+    ax = [(axes[i] if axes else 7) for i in proj]
+    uniform = len(set(ax)) <= 1
+    gram_pass = (ortho and k > 1) or bool(proj)
     return {
         "k_plane_fwd": sites * (reads * w + k * s),
         "k_columns": sites * k * 2 * s,
         "k_plane_inv": sites * (k * s + reads * w + k * w + k * w),
-        "k_project": sites * sum(2 * w for i in range(k) if parity and parity[i]),
-        "k_gram": sites * k * w if (ortho and k > 1) else 0.0,
+        "k_project": 0.0 if uniform else sites * 2 * w * len(proj),
+        "k_project_gram": sites * (k * w + (len(proj) * w if uniform else 0)) if gram_pass else 0.0,
         "k_finalize": 0.0,
     }
 
@@ -104,7 +110,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 256 MiB five times (scale for HBM counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": x.numel() * 4, "copies": 5}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs one lattice per GPU on a single GPU; "
                                    "--gpus must be 1 (multi-GPU sharding is described in DESIGN.md, "
@@ -116,6 +133,10 @@ def main():
 
     torch.cuda.set_device(0)
     n = args.n
+    # schedule per (n, precision) picked by the library's autotuner (timed outside the
+    # measured region; results are deterministic for a given schedule)
+    tune32 = json.loads(itse.autotune(n, "fp32"))
+    tune64 = None if args.no_fp64 else json.loads(itse.autotune(n, "fp64"))
     p, v32, st32 = build_workload(n, fp32=True)
     lat = make_lattice(itse, p, v32, st32, fp32=True)
     secs = timed_steps(torch, lat, args.steps, args.warmup)
@@ -158,7 +179,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"precision form: {n}^3, 3 states (parity +,-,- with Gram-Schmidt), "
                                f"FP32 states/FFT, FP64 reductions, sqrt(p^2+m^2)-m, Cornell+aniso FP32 V",
-                   "n": n, "nstates": p.nstates, "site_steps_per_step": sites},
+                   "n": n, "nstates": p.nstates, "site_steps_per_step": sites,
+                   "schedule": json.loads(itse.schedule(n, "fp32")), "autotune_fp32": tune32,
+                   "autotune_fp64": tune64},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
                      "kernel_ms": dom_ms, "kernel_bytes": pb[dom]},

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -226,25 +227,43 @@ extern "C" itse_status itse_autotune(int n, int precision, void *stream, char *j
         d.dtau = 0.025;
         d.precision = precision;
         d.center = ITSE_CENTER_ORIGIN;
-        d.nstates = 1;
+        // three states (even, odd, odd deflated against the odd one): every kernel of
+        // a step runs, with distinct deterministic states so that the Gram matrix is
+        // well conditioned
+        d.nstates = 3;
         itse_lattice *L = nullptr;
         itse_status st = itse_create(&d, stream, nullptr, nullptr, nullptr, &L);
         if (st) return st;
-        std::vector<double> psi((size_t)n * n * n, 1.0);
-        st = itse_set_state(L, 0, psi.data(), ITSE_DTYPE_F64, 0);
-        if (!st) st = itse_step(L, 3, nullptr);
-        hipEvent_t e0, e1;
-        (void)hipEventCreate(&e0);
-        (void)hipEventCreate(&e1);
-        (void)hipEventRecord(e0, (hipStream_t)stream);
+        const size_t n3 = (size_t)n * n * n;
+        std::vector<double> psi(n3);
+        for (int i = 0; i < d.nstates && !st; ++i) {
+            for (size_t e = 0; e < n3; ++e) psi[e] = std::sin(0.37 * (double)(e % 100003) * (i + 1)) + 0.1 * i;
+            st = itse_set_state(L, i, psi.data(), ITSE_DTYPE_F64, 0);
+        }
+        itse_step_opts o{};
+        o.ortho_every = 1;
+        o.parity[0] = 1;
+        o.parity[1] = -1;
+        o.parity[2] = -1;
+        for (int i = 0; i < ITSE_MAX_STATES; ++i) o.axes[i] = 7;
+        if (!st) st = itse_step(L, 3, &o);
         const int reps = n >= 192 ? 10 : 30;
-        if (!st) st = itse_step(L, reps, nullptr);
-        (void)hipEventRecord(e1, (hipStream_t)stream);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        float ms = 1e30f;
+        for (int trial = 0; trial < 2 && !st; ++trial) {
+            hipEvent_t e0, e1;
+            (void)hipEventCreate(&e0);
+            (void)hipEventCreate(&e1);
+            (void)hipEventRecord(e0, (hipStream_t)stream);
+            st = itse_step(L, reps, nullptr);
+            (void)hipEventRecord(e1, (hipStream_t)stream);
+            (void)hipEventSynchronize(e1);
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            ms = std::min(ms, t);
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+        }
+        if (!st) st = itse_sync(L);
         itse_destroy(L);
         if (st) return st;
         ms /= reps;

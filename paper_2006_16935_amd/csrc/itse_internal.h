@@ -55,14 +55,18 @@ struct LatDev {
     double *part_proj;   // [MAXK][nb_proj]
     double *part_gram;   // [nb_gram][MAXK*(MAXK+1)/2]
     int nb_rows, nb_cols, nb_proj, nb_gram;
+    int pg_chunks;            // workgroups per plane of the projection/Gram kernel
     // options
     int ortho_every, moments;
     int psign[MAXK], paxes[MAXK];
+    int proj_mode;            // 0 no projection, 1 all projected states share proj_axes, 2 mixed axes
+    int proj_axes;
     // dynamic state
     double coef[MAXK][MAXK];  // current state i = sum_j coef[j][i] u[j]
     long long step;
     int error;                // bit0 non-finite, bit1 Gram not positive definite, bit2 unstable V
-    int pad_;
+    int fin_count;            // finalisation workgroups done this step (reset by the last)
+    double fin_sums[MAXK * (NQR + NQC) + MAXK * (MAXK + 1) / 2];
     ObsDev obs[MAXK];
     ObsDev *hist;             // [HIST_CAP][MAXK]
 };
@@ -102,7 +106,8 @@ struct Launch {
     static hipError_t plane_inv(int n, int variant, int mode, const JobRef *jobs, int njobs, hipStream_t s);
     static hipError_t project(int n, const JobRef *jobs, int njobs, int force_sign, int force_axes, int which,
                               hipStream_t s);
-    static hipError_t gram(int n, int kmax, const JobRef *lats, int nlats, int force, int which, hipStream_t s);
+    static hipError_t project_gram(int n, int kmax, const JobRef *lats, int nlats, int force, int which,
+                                   hipStream_t s);
     static hipError_t combine(int n, const JobRef *jobs, int njobs, void *const *outs, hipStream_t s);
     static hipError_t convert_in(const void *src, int src_dtype, void *dst, size_t count, hipStream_t s);
     static hipError_t convert_out(const void *src, void *dst, int dst_dtype, size_t count, hipStream_t s);
@@ -113,6 +118,25 @@ hipError_t launch_check_potential(const LatDev *lat, int prec, hipStream_t s);
 
 // Workgroups of the flat kernels (Gram sums, combination): a fixed count per n,
 // so that the partial-sum layout and the summation order do not change.
+// Row stride (complex values) of the stored half spectra along kz: N/2 + 1 rounded
+// up to whole 128-byte lines.
+template <typename R>
+__host__ __device__ constexpr int spec_row_stride(int n) {
+    constexpr int per_line = 128 / (2 * (int)sizeof(R));
+    return ((n / 2 + 1 + per_line - 1) / per_line) * per_line;
+}
+inline size_t spec_bytes(int n, int prec) {
+    const size_t hs = prec == ITSE_FP32 ? spec_row_stride<float>(n) : spec_row_stride<double>(n);
+    const size_t w = prec == ITSE_FP32 ? 4 : 8;
+    return (size_t)n * n * hs * 2 * w;
+}
+
+// Workgroups per plane of the projection/Gram kernel (about 4096 sites each).
+inline int pg_chunks(int n) {
+    const int c = n * n / 4096;
+    return c < 1 ? 1 : c;
+}
+
 inline int flat_blocks(int n) {
     const long long n3 = (long long)n * n * n;
     const long long b = (n3 + 4 * NT - 1) / (4 * NT);

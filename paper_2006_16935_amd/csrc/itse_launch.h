@@ -18,7 +18,7 @@ struct NVariants<float, 128> {
 };
 template <>
 struct NVariants<float, 256> {
-    static constexpr int value = 2;
+    static constexpr int value = 3;
 };
 template <>
 struct NVariants<double, 256> {
@@ -36,7 +36,7 @@ static Sched sched_of() {
     s.nb_rows = G::NB_PLANE;
     s.nb_cols = G::NB_COLS;
     s.nb_proj = N;
-    s.nb_gram = flat_blocks(N);
+    s.nb_gram = N * pg_chunks(N);
     s.lds_plane = (int)(G::PLANE_ELEMS * sizeof(C2<R>) + N * sizeof(C2<R>));
     s.lds_cols = (int)(N * G::CS * sizeof(C2<R>) + N * sizeof(C2<R>) + N * sizeof(double));
     return s;
@@ -49,7 +49,10 @@ static hipError_t dispatch(int n, int variant, F f) {
 #define ITSE_CASE(NN)                                                                  \
     case NN:                                                                           \
         if (variant == 0 || NVariants<R, NN>::value == 1) return f.template operator()<NN, 0>(); \
-        if constexpr (NVariants<R, NN>::value > 1) return f.template operator()<NN, 1>(); \
+        if constexpr (NVariants<R, NN>::value > 1)                                     \
+            if (variant == 1) return f.template operator()<NN, 1>();                   \
+        if constexpr (NVariants<R, NN>::value > 2)                                     \
+            if (variant == 2) return f.template operator()<NN, 2>();                   \
         return hipErrorInvalidValue;
         ITSE_FOR_EACH_N(ITSE_CASE)
 #undef ITSE_CASE
@@ -171,13 +174,15 @@ hipError_t Launch<R>::project(int n, const JobRef *jobs, int njobs, int force_si
 }
 
 template <typename R>
-hipError_t Launch<R>::gram(int n, int kmax, const JobRef *lats, int nlats, int force, int which, hipStream_t s) {
-    if (nlats <= 0 || kmax < 2) return hipSuccess;
-    const dim3 grid(flat_blocks(n), nlats);
-    if (kmax <= 2) hipLaunchKernelGGL((k_gram<R, 2>), grid, dim3(NT), 0, s, lats, force, which);
-    else if (kmax <= 3) hipLaunchKernelGGL((k_gram<R, 3>), grid, dim3(NT), 0, s, lats, force, which);
-    else if (kmax <= 4) hipLaunchKernelGGL((k_gram<R, 4>), grid, dim3(NT), 0, s, lats, force, which);
-    else hipLaunchKernelGGL((k_gram<R, MAXK>), grid, dim3(NT), 0, s, lats, force, which);
+hipError_t Launch<R>::project_gram(int n, int kmax, const JobRef *lats, int nlats, int force, int which,
+                                   hipStream_t s) {
+    if (nlats <= 0) return hipSuccess;
+    const dim3 grid(n * pg_chunks(n), nlats);
+    if (kmax <= 1) hipLaunchKernelGGL((k_project_gram<R, 1>), grid, dim3(NT), 0, s, lats, force, which);
+    else if (kmax <= 2) hipLaunchKernelGGL((k_project_gram<R, 2>), grid, dim3(NT), 0, s, lats, force, which);
+    else if (kmax <= 3) hipLaunchKernelGGL((k_project_gram<R, 3>), grid, dim3(NT), 0, s, lats, force, which);
+    else if (kmax <= 4) hipLaunchKernelGGL((k_project_gram<R, 4>), grid, dim3(NT), 0, s, lats, force, which);
+    else hipLaunchKernelGGL((k_project_gram<R, MAXK>), grid, dim3(NT), 0, s, lats, force, which);
     return hipGetLastError();
 }
 

@@ -32,6 +32,32 @@
 
 namespace itse {
 
+// Pointers into device memory that the compiler should address as global memory
+// (global_load/store instead of flat accesses, which also count against the LDS
+// wait counter).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define ITSE_GLOBAL __attribute__((address_space(1)))
+#else
+#define ITSE_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ ITSE_GLOBAL T *gmem(T *p) {
+    return (ITSE_GLOBAL T *)p;
+}
+template <typename T>
+__device__ __forceinline__ const ITSE_GLOBAL T *gmem(const T *p) {
+    return (const ITSE_GLOBAL T *)p;
+}
+
+// Workgroup index remapped so that consecutive indices run on one XCD: the
+// hardware hands workgroup b to XCD b mod 8, so XCD k gets the contiguous range
+// [k nb/8, (k+1) nb/8) in dispatch order (a tail of nb mod 8 keeps its index).
+__device__ __forceinline__ int xcd_local_index(int b, int nb) {
+    const int full = nb & ~7;
+    if (b >= full) return b;
+    return (b & 7) * (full >> 3) + (b >> 3);
+}
+
 // ---------------------------------------------------------------------------
 // Schedules: split factor S (sub-planes per plane), waves per workgroup in the
 // plane passes (NWP) and the column pass (NWC), kz columns per column-pass
@@ -47,6 +73,8 @@ struct Plan;
         static constexpr int S = S_, NWP = NWP_, W = W_, NWC = NWC_; \
     };
 
+// Column-pass chunks of W complex values are 128 bytes (W = 16 FP32, 8 FP64) from
+// N = 48 up, so that the strided reads along x fetch whole cache lines.
 // FP32: variant 0 is the default.
 ITSE_PLAN(float, 8, 0, 1, 1, 5, 1)
 ITSE_PLAN(float, 12, 0, 1, 1, 7, 1)
@@ -57,10 +85,11 @@ ITSE_PLAN(float, 48, 0, 1, 4, 16, 1)
 ITSE_PLAN(float, 64, 0, 1, 4, 16, 1)
 ITSE_PLAN(float, 96, 0, 1, 4, 16, 2)
 ITSE_PLAN(float, 128, 0, 1, 8, 16, 2)
-ITSE_PLAN(float, 192, 0, 2, 8, 8, 4)
-ITSE_PLAN(float, 256, 0, 4, 8, 8, 8)
+ITSE_PLAN(float, 128, 1, 2, 4, 16, 4)
+ITSE_PLAN(float, 192, 0, 2, 8, 16, 8)
+ITSE_PLAN(float, 256, 0, 4, 8, 16, 16)
 ITSE_PLAN(float, 256, 1, 2, 8, 16, 8)
-ITSE_PLAN(float, 128, 1, 2, 4, 8, 2)
+ITSE_PLAN(float, 256, 2, 4, 8, 8, 8)
 // FP64
 ITSE_PLAN(double, 8, 0, 1, 1, 5, 1)
 ITSE_PLAN(double, 12, 0, 1, 1, 7, 1)
@@ -71,8 +100,8 @@ ITSE_PLAN(double, 48, 0, 1, 4, 8, 1)
 ITSE_PLAN(double, 64, 0, 1, 4, 8, 1)
 ITSE_PLAN(double, 96, 0, 1, 4, 8, 2)
 ITSE_PLAN(double, 128, 0, 2, 4, 8, 2)
-ITSE_PLAN(double, 192, 0, 4, 4, 4, 4)
-ITSE_PLAN(double, 256, 0, 4, 8, 4, 4)
+ITSE_PLAN(double, 192, 0, 4, 4, 8, 8)
+ITSE_PLAN(double, 256, 0, 4, 8, 8, 8)
 ITSE_PLAN(double, 256, 1, 8, 4, 4, 8)
 #undef ITSE_PLAN
 
@@ -99,8 +128,16 @@ struct Geo {
     static constexpr int LSZ = 2 * HP;
     static constexpr int PLANE_ELEMS = M * HP;
     static constexpr int NTP = 64 * NWP;
+    // plane workgroups that fit one CU's 160 KiB of LDS (at most 2), and the waves
+    // per SIMD they need (caps the registers so that they do fit)
+    static constexpr int LDS_PLANE = PLANE_ELEMS * (int)sizeof(C2<R>) + N * (int)sizeof(C2<R>) + 64 * NQR;
+    static constexpr int WG_CU = (163840 / LDS_PLANE) >= 2 ? 2 : 1;
+    static constexpr int WPE = (WG_CU * NWP + 3) / 4 > 1 ? (WG_CU * NWP + 3) / 4 : 1;
     // Column pass
     static constexpr int NCH = (H + W - 1) / W;      // kz chunks
+    // Row stride of the stored sub-spectra: H rounded up to whole 128-byte lines,
+    // so that the column pass's chunks of W values start on a line.
+    static constexpr int HS = spec_row_stride<R>(N);
     static constexpr int LINES = S * W;              // x lines per column workgroup
     static_assert(LINES % NWC == 0, "lines split evenly over waves");
     static constexpr int LPWC = LINES / NWC;
@@ -160,7 +197,7 @@ __device__ __forceinline__ void block_sums(double (&acc)[Q], double *dst, double
 // Lattice fields used by the passes, copied out of the device record once.
 template <typename R>
 struct LatView {
-    const R *u[MAXK];
+    const ITSE_GLOBAL R *u[MAXK];
     double c[MAXK];
     int i;
 };
@@ -170,7 +207,7 @@ __device__ __forceinline__ void load_view(LatView<R> &vw, const LatDev &L, int i
     vw.i = i;
 #pragma unroll
     for (int j = 0; j < MAXK; ++j) {
-        vw.u[j] = (const R *)state_buf(L, L.step, 0, j);
+        vw.u[j] = gmem((const R *)state_buf(L, L.step, 0, j));
         vw.c[j] = (j <= i) ? L.coef[j][i] : 0.0;
     }
 }
@@ -186,11 +223,109 @@ __device__ __forceinline__ R lazy_psi(const LatView<R> &vw, size_t off) {
     return (R)s;
 }
 
+// 16-byte vector of R (4 floats or 2 doubles): one global load or store.
+template <typename R>
+constexpr int VLEN = 16 / (int)sizeof(R);
+template <typename R>
+using Vec = R __attribute__((ext_vector_type(VLEN<R>)));
+
+// Current states of rows y0 and y1 of plane x over G chunks of VLEN consecutive
+// z (chunk t of the calling lane starts at z0[t]): psi = sum_(j<=i) c_j u_j in
+// FP64, rounded once.  All loads of one array are issued before any use.
+template <typename R, int G>
+__device__ __forceinline__ void lazy_rows(const LatView<R> &vw, const size_t (&o0)[G], const size_t (&o1)[G],
+                                          const bool (&ok)[G], R (&p0)[G][VLEN<R>], R (&p1)[G][VLEN<R>]) {
+    constexpr int VL = VLEN<R>;
+    double a0[G][VL], a1[G][VL];
+#pragma unroll
+    for (int t = 0; t < G; ++t)
+#pragma unroll
+        for (int k = 0; k < VL; ++k) a0[t][k] = a1[t][k] = 0.0;
+#pragma unroll
+    for (int j = 0; j < MAXK; ++j) {
+        if (j > vw.i) break;
+        const double c = vw.c[j];
+        if (c == 0.0) continue;
+        Vec<R> v0[G], v1[G];
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+            if (ok[t]) {
+                v0[t] = *(const ITSE_GLOBAL Vec<R> *)(vw.u[j] + o0[t]);
+                v1[t] = *(const ITSE_GLOBAL Vec<R> *)(vw.u[j] + o1[t]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < G; ++t)
+#pragma unroll
+            for (int k = 0; k < VL; ++k) {
+                a0[t][k] += c * (double)v0[t][k];
+                a1[t][k] += c * (double)v1[t][k];
+            }
+    }
+#pragma unroll
+    for (int t = 0; t < G; ++t)
+#pragma unroll
+        for (int k = 0; k < VL; ++k) {
+            p0[t][k] = (R)a0[t][k];
+            p1[t][k] = (R)a1[t][k];
+        }
+}
+
+// Chunks of the row pairs a wave owns: PPW pairs x N/VLEN chunks, taken by the 64
+// lanes in groups of G per lane.
+template <typename R, int N, int PPW, int GMAX>
+struct PairChunks {
+    static constexpr int VL = VLEN<R>;
+    static constexpr int CPR = N / VL;                 // chunks per row
+    static constexpr int TOTAL = PPW * CPR;            // chunks per wave
+    static constexpr int PER_LANE = (TOTAL + 63) / 64;
+    static constexpr int G = PER_LANE < GMAX ? PER_LANE : GMAX;
+    static constexpr int GROUPS = (PER_LANE + G - 1) / G;
+    static_assert(N % VLEN<R> == 0, "rows hold whole vectors");
+};
+
+// Copy of a contiguous global block of E complex values into LDS rows of length
+// RL with stride RS, all loads of the calling thread issued first.
+template <typename R, int E, int RL, int GS, int RS, int NTH>
+__device__ __forceinline__ void block_load_rows(const C2<R> *src_, C2<R> *dst, int tid) {
+    const ITSE_GLOBAL C2<R> *src = gmem(src_);
+    constexpr int T = (E + NTH - 1) / NTH;
+    constexpr int TB = 32 / (int)sizeof(C2<R>) * 2;  // loads in flight per batch: 8 (FP32), 4 (FP64)
+#pragma unroll
+    for (int t0 = 0; t0 < T; t0 += TB) {
+        C2<R> v[TB];
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            // out-of-range threads load the last element (valid) and store nothing
+            const int e = tid + (t0 + t) * NTH;
+            const int ee = (E % NTH == 0 || e < E) ? e : E - 1;
+            if (t0 + t < T) v[t] = src[(ee / RL) * GS + ee % RL];
+        }
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+            const int e = tid + (t0 + t) * NTH;
+            if (t0 + t < T && (E % NTH == 0 || e < E)) dst[(e / RL) * RS + e % RL] = v[t];
+        }
+    }
+}
+
+template <typename R, int E, int RL, int GS, int RS, int NTH>
+__device__ __forceinline__ void block_store_rows(const C2<R> *src, C2<R> *dst_, int tid) {
+    ITSE_GLOBAL C2<R> *dst = gmem(dst_);
+    constexpr int T = (E + NTH - 1) / NTH;
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int e = tid + t * NTH;
+        if (E % NTH == 0 || e < E) dst[(e / RL) * GS + e % RL] = src[(e / RL) * RS + e % RL];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // P1: forward plane pass.  grid.x = x * S + r, grid.y = job.
 // ---------------------------------------------------------------------------
 template <typename R, int N, int V>
-__global__ void __launch_bounds__((Geo<R, N, V>::NTP)) k_plane_fwd(const JobRef *__restrict__ jobs) {
+__global__ void __launch_bounds__((Geo<R, N, V>::NTP)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPE)))
+k_plane_fwd(const JobRef *__restrict__ jobs) {
     using G = Geo<R, N, V>;
     constexpr int S = G::S, M = G::M, H = G::H, HP = G::HP, LSZ = G::LSZ, PPW = G::PPW, CPW = G::CPW;
     __shared__ C2<R> buf[G::PLANE_ELEMS];
@@ -207,12 +342,34 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTP)) k_plane_fwd(const JobRef 
 
     // rows of this wave's pairs -> packed complex rows (z along the line)
     const int p0 = wv * PPW;
-    for (int e = lane; e < PPW * N; e += 64) {
-        const int pl = e / N, z = e % N;
-        const int p = p0 + pl;
-        const int y0 = r + S * (2 * p), y1 = y0 + S;
-        const size_t o0 = ((size_t)x * N + y0) * N + z, o1 = ((size_t)x * N + y1) * N + z;
-        buf[p * LSZ + z] = C2<R>{lazy_psi(vw, o0), lazy_psi(vw, o1)};
+    {
+        using PC = PairChunks<R, N, PPW, 2>;
+        constexpr int VL = PC::VL, G = PC::G;
+#pragma unroll 1
+        for (int gi = 0; gi < PC::GROUPS; ++gi) {
+            size_t o0[G], o1[G];
+            bool ok[G];
+            int lp[G];
+#pragma unroll
+            for (int t = 0; t < G; ++t) {
+                const int c = lane + 64 * (gi * G + t);
+                ok[t] = c < PC::TOTAL;
+                const int pl = ok[t] ? c / PC::CPR : 0, z = ok[t] ? (c % PC::CPR) * VL : 0;
+                const int p = p0 + pl;
+                const int y0 = r + S * (2 * p);
+                o0[t] = ((size_t)x * N + y0) * N + z;
+                o1[t] = o0[t] + (size_t)S * N;
+                lp[t] = p * LSZ + z;
+            }
+            R v0[G][VL], v1[G][VL];
+            lazy_rows<R, G>(vw, o0, o1, ok, v0, v1);
+#pragma unroll
+            for (int t = 0; t < G; ++t)
+                if (ok[t]) {
+#pragma unroll
+                    for (int k = 0; k < VL; ++k) buf[lp[t] + k] = C2<R>{v0[t][k], v1[t][k]};
+                }
+        }
     }
     __syncthreads();  // twiddles
     WaveFft<R, N, PPW, -1, false, 1>::run(buf + p0 * LSZ, LSZ, 1, tw, lane);
@@ -247,11 +404,7 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTP)) k_plane_fwd(const JobRef 
     WaveFft<R, M, CPW, -1, true, S>::run(buf + wv * CPW, 1, HP, tw, lane);
     if (wv == G::NWP - 1) WaveFft<R, M, 1, -1, true, S>::run(buf + N / 2, 1, HP, tw, lane);
     __syncthreads();
-    C2<R> *dst = spec + ((size_t)r * N + x) * M * H;
-    for (int e = tid; e < M * H; e += G::NTP) {
-        const int ky = e / H, kz = e % H;
-        dst[e] = buf[ky * HP + kz];
-    }
+    block_store_rows<R, M * H, H, G::HS, HP, G::NTP>(buf, spec + ((size_t)r * N + x) * M * G::HS, tid);
 }
 
 // ---------------------------------------------------------------------------
@@ -274,34 +427,43 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTC)) k_columns(const JobRef *_
     const LatDev &L = *job.lat;
     const int i = job.state;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int kyp = blockIdx.x / G::NCH, kz0 = (blockIdx.x % G::NCH) * W;
+    // consecutive chunks of one ky' row share cache lines: keep them on one XCD
+    const int blk = xcd_local_index(blockIdx.x, gridDim.x);
+    const int kyp = blk / G::NCH, kz0 = (blk % G::NCH) * W;
     const C2<R> *twg = (const C2<R> *)L.tw;
     for (int e = tid; e < N; e += NTC) {
         tw[e] = twg[e];
         ktab[e] = L.ktab[e];
     }
     __syncthreads();
-    C2<R> *spec = (C2<R> *)L.spec[i];
-    const size_t sub = (size_t)N * M * H;  // one sub-spectrum
-    // load S sub-spectra values, combine over r -> S full-y columns ky = ky' + M q
-    for (int e = tid; e < N * W; e += NTC) {
-        const int xx = e / W, w = e % W, kz = kz0 + w;
-        C2<R> v[S];
-        if (kz < H) {
-            const size_t base = ((size_t)xx * M + kyp) * H + kz;
+    ITSE_GLOBAL C2<R> *spec = gmem((C2<R> *)L.spec[i]);
+    constexpr int HS = G::HS;
+    const size_t sub = (size_t)N * M * HS;  // one sub-spectrum
+    // load S sub-spectra values (all loads of the thread first), combine over r ->
+    // S full-y columns ky = ky' + M q
+    {
+        constexpr int T = (N * W + NTC - 1) / NTC;
+        C2<R> v[T][S];
 #pragma unroll
-            for (int rr = 0; rr < S; ++rr) {
-                C2<R> a = spec[rr * sub + base];
-                if (rr > 0) a = cmul(a, tw[rr * kyp]);
-                v[rr] = a;
-            }
-            Dft<S, -1, R>::run(v);
-        } else {
+        for (int t = 0; t < T; ++t) {
+            const int e = tid + t * NTC;
+            const int xx = e / W, kz = kz0 + e % W;
+            const bool ok = ((N * W) % NTC == 0 || e < N * W) && kz < H;
+            const size_t base = ((size_t)xx * M + kyp) * HS + kz;
 #pragma unroll
-            for (int rr = 0; rr < S; ++rr) v[rr] = C2<R>{(R)0, (R)0};
+            for (int rr = 0; rr < S; ++rr) v[t][rr] = ok ? spec[rr * sub + base] : C2<R>{(R)0, (R)0};
         }
 #pragma unroll
-        for (int q = 0; q < S; ++q) buf[xx * CS + q * W + w] = v[q];
+        for (int t = 0; t < T; ++t) {
+            const int e = tid + t * NTC;
+            if ((N * W) % NTC != 0 && e >= N * W) continue;
+            const int xx = e / W, w = e % W;
+#pragma unroll
+            for (int rr = 1; rr < S; ++rr) v[t][rr] = cmul(v[t][rr], tw[rr * kyp]);
+            Dft<S, -1, R>::run(v[t]);
+#pragma unroll
+            for (int q = 0; q < S; ++q) buf[xx * CS + q * W + w] = v[t][q];
+        }
     }
     __syncthreads();
     const int l0 = wv * LPW;
@@ -310,7 +472,7 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTC)) k_columns(const JobRef *_
         __syncthreads();
         for (int e = tid; e < N * S * W; e += NTC) {
             const int xx = e / (S * W), l = e % (S * W), q = l / W, w = l % W, kz = kz0 + w;
-            if (kz < H) out[((size_t)xx * N + kyp + M * q) * H + kz] = buf[xx * CS + l];
+            if (kz < H) gmem(out)[((size_t)xx * N + kyp + M * q) * H + kz] = buf[xx * CS + l];
         }
         return;
     }
@@ -347,7 +509,7 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTC)) k_columns(const JobRef *_
     }
     __builtin_amdgcn_wave_barrier();
     WaveFft<R, N, LPW, +1, true, 1>::run(buf + l0, 1, CS, tw, lane);
-    if (mom) block_sums<NQC, NTC>(acc, L.part_cols + ((size_t)i * L.nb_cols + blockIdx.x) * NQC, red);
+    if (mom) block_sums<NQC, NTC>(acc, L.part_cols + ((size_t)i * L.nb_cols + blk) * NQC, red);
     __syncthreads();
     for (int e = tid; e < N * W; e += NTC) {
         const int xx = e / W, w = e % W, kz = kz0 + w;
@@ -356,7 +518,7 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTC)) k_columns(const JobRef *_
 #pragma unroll
         for (int q = 0; q < S; ++q) v[q] = buf[xx * CS + q * W + w];
         Dft<S, +1, R>::run(v);
-        const size_t base = ((size_t)xx * M + kyp) * H + kz;
+        const size_t base = ((size_t)xx * M + kyp) * HS + kz;
 #pragma unroll
         for (int rr = 0; rr < S; ++rr) {
             C2<R> a = v[rr];
@@ -372,7 +534,8 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTC)) k_columns(const JobRef *_
 // mode INV_EVAL: sums only; INV_KOUT: K psi written to L.kout.
 // ---------------------------------------------------------------------------
 template <typename R, int N, int V>
-__global__ void __launch_bounds__((Geo<R, N, V>::NTP)) k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
+__global__ void __launch_bounds__((Geo<R, N, V>::NTP)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPE)))
+k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     using G = Geo<R, N, V>;
     constexpr int S = G::S, M = G::M, H = G::H, HP = G::HP, LSZ = G::LSZ, PPW = G::PPW, CPW = G::CPW;
     constexpr int NTP = G::NTP;
@@ -386,11 +549,8 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTP)) k_plane_inv(const JobRef 
     const int x = blockIdx.x / S, r = blockIdx.x % S;
     const C2<R> *twg = (const C2<R> *)L.tw;
     for (int e = tid; e < N; e += NTP) tw[e] = twg[e];
-    const C2<R> *src = (const C2<R> *)L.spec[i] + ((size_t)r * N + x) * M * H;
-    for (int e = tid; e < M * H; e += NTP) {
-        const int ky = e / H, kz = e % H;
-        buf[ky * HP + kz] = src[e];
-    }
+    block_load_rows<R, M * H, H, G::HS, HP, NTP>((const C2<R> *)L.spec[i] + ((size_t)r * N + x) * M * G::HS,
+                                                 buf, tid);
     __syncthreads();
     WaveFft<R, M, CPW, +1, true, S>::run(buf + wv * CPW, 1, HP, tw, lane);
     if (wv == G::NWP - 1) WaveFft<R, M, 1, +1, true, S>::run(buf + N / 2, 1, HP, tw, lane);
@@ -430,9 +590,9 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTP)) k_plane_inv(const JobRef 
     // update of this wave's rows
     LatView<R> vw;
     load_view(vw, L, i);
-    const R *v = (const R *)L.v;
-    R *u = (R *)state_buf(L, L.step, 1, i);
-    R *kout = (R *)L.kout;
+    const ITSE_GLOBAL R *v = gmem((const R *)L.v);
+    ITSE_GLOBAL R *u = gmem((R *)state_buf(L, L.step, 1, i));
+    ITSE_GLOBAL R *kout = gmem((R *)L.kout);
     const R h = (R)L.h, dt = (R)L.dtau;
     const bool mom = L.moments != 0;
     const int center = L.center;
@@ -440,35 +600,77 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTP)) k_plane_inv(const JobRef 
     double acc[NQR];
 #pragma unroll
     for (int q = 0; q < NQR; ++q) acc[q] = 0.0;
-    for (int e = lane; e < PPW * N; e += 64) {
-        const int pl = e / N, z = e % N;
-        const int p = p0 + pl;
-        const C2<R> kp = buf[p * LSZ + z];
+    using PC = PairChunks<R, N, PPW, 1>;
+    constexpr int VL = PC::VL, GG = PC::G;
+    const double cx = site_coord(x, N, center, a);
+#pragma unroll 1
+    for (int gi = 0; gi < PC::GROUPS; ++gi) {
+        size_t o0[GG], o1[GG];
+        bool ok[GG];
+        int lp[GG], yy[GG], zz0[GG];
 #pragma unroll
-        for (int row = 0; row < 2; ++row) {
-            const int y = r + S * (2 * p + row);
-            const size_t off = ((size_t)x * N + y) * N + z;
-            const R kv = row == 0 ? kp.x : kp.y;
-            const R ph = lazy_psi(vw, off);
-            const R vv = v[off];
-            const R hv = h * vv;
-            const R un = (ph * ((R)1 - hv) - dt * kv) / ((R)1 + hv);
-            if (mode == INV_UPDATE) u[off] = un;
-            else if (mode == INV_KOUT) kout[off] = kv;
-            const double pd = (double)ph;
-            acc[RQ_PP] += pd * pd;
-            acc[RQ_PK] += pd * (double)kv;
-            acc[RQ_VPP] += (double)vv * pd * pd;
-            acc[RQ_UU] += (double)un * (double)un;
-            if (mom) {
-                const double cx = site_coord(x, N, center, a);
-                const double cy = site_coord(y, N, center, a);
-                const double cz = site_coord(z, N, center, a);
-                const double w2 = pd * pd;
-                acc[RQ_X] += cx * w2;
-                acc[RQ_Y] += cy * w2;
-                acc[RQ_Z] += cz * w2;
-                acc[RQ_R2] += (cx * cx + cy * cy + cz * cz) * w2;
+        for (int t = 0; t < GG; ++t) {
+            const int c = lane + 64 * (gi * GG + t);
+            ok[t] = c < PC::TOTAL;
+            const int pl = ok[t] ? c / PC::CPR : 0, z = ok[t] ? (c % PC::CPR) * VL : 0;
+            const int p = p0 + pl;
+            yy[t] = r + S * (2 * p);
+            zz0[t] = z;
+            o0[t] = ((size_t)x * N + yy[t]) * N + z;
+            o1[t] = o0[t] + (size_t)S * N;
+            lp[t] = p * LSZ + z;
+        }
+        R ph[2][GG][VL];
+        lazy_rows<R, GG>(vw, o0, o1, ok, ph[0], ph[1]);
+        Vec<R> vv[2][GG];
+#pragma unroll
+        for (int t = 0; t < GG; ++t)
+            if (ok[t]) {
+                vv[0][t] = *(const ITSE_GLOBAL Vec<R> *)(v + o0[t]);
+                vv[1][t] = *(const ITSE_GLOBAL Vec<R> *)(v + o1[t]);
+            }
+#pragma unroll
+        for (int t = 0; t < GG; ++t) {
+            if (!ok[t]) continue;
+            Vec<R> un[2], kv[2];
+#pragma unroll
+            for (int k = 0; k < VL; ++k) {
+                const C2<R> kp = buf[lp[t] + k];
+                kv[0][k] = kp.x;
+                kv[1][k] = kp.y;
+            }
+#pragma unroll
+            for (int row = 0; row < 2; ++row) {
+                const double cy = site_coord(yy[t] + row * S, N, center, a);
+#pragma unroll
+                for (int k = 0; k < VL; ++k) {
+                    const R p_ = ph[row][t][k];
+                    const R vr = vv[row][t][k];
+                    const R kr = kv[row][k];
+                    const R hv = h * vr;
+                    const R unv = (p_ * ((R)1 - hv) - dt * kr) / ((R)1 + hv);
+                    un[row][k] = unv;
+                    const double pd = (double)p_;
+                    acc[RQ_PP] += pd * pd;
+                    acc[RQ_PK] += pd * (double)kr;
+                    acc[RQ_VPP] += (double)vr * pd * pd;
+                    acc[RQ_UU] += (double)unv * (double)unv;
+                    if (mom) {
+                        const double cz = site_coord(zz0[t] + k, N, center, a);
+                        const double w2 = pd * pd;
+                        acc[RQ_X] += cx * w2;
+                        acc[RQ_Y] += cy * w2;
+                        acc[RQ_Z] += cz * w2;
+                        acc[RQ_R2] += (cx * cx + cy * cy + cz * cz) * w2;
+                    }
+                }
+            }
+            if (mode == INV_UPDATE) {
+                *(ITSE_GLOBAL Vec<R> *)(u + o0[t]) = un[0];
+                *(ITSE_GLOBAL Vec<R> *)(u + o1[t]) = un[1];
+            } else if (mode == INV_KOUT) {
+                *(ITSE_GLOBAL Vec<R> *)(kout + o0[t]) = kv[0];
+                *(ITSE_GLOBAL Vec<R> *)(kout + o1[t]) = kv[1];
             }
         }
     }
@@ -489,7 +691,7 @@ __global__ void __launch_bounds__(NT) k_project(const JobRef *__restrict__ jobs,
     const JobRef job = jobs[blockIdx.y];
     const LatDev &L = *job.lat;
     const int i = job.state;
-    const int sign = force_sign ? force_sign : L.psign[i];
+    const int sign = force_sign ? force_sign : (L.proj_mode == 2 ? L.psign[i] : 0);
     const int axes = force_sign ? force_axes : L.paxes[i];
     const int n = L.n, center = L.center;
     const int x = blockIdx.x;
@@ -501,11 +703,12 @@ __global__ void __launch_bounds__(NT) k_project(const JobRef *__restrict__ jobs,
         if (threadIdx.x == 0) *dst = 0.0;
         return;
     }
-    R *u = (R *)state_buf(L, L.step, which, i);
+    ITSE_GLOBAL R *u = gmem((R *)state_buf(L, L.step, which, i));
     const size_t n2 = (size_t)n * n;
-    R *pa_ = u + (size_t)x * n2;
-    R *pb_ = u + (size_t)xm * n2;
+    ITSE_GLOBAL R *pa_ = u + (size_t)x * n2;
+    ITSE_GLOBAL R *pb_ = u + (size_t)xm * n2;
     const R sg = (R)sign;
+#pragma unroll 4
     for (int e = threadIdx.x; e < (int)n2; e += NT) {
         const int y = e / n, z = e % n;
         const int ym = (axes & 2) ? mirror_idx(y, n, center) : y;
@@ -528,38 +731,124 @@ __global__ void __launch_bounds__(NT) k_project(const JobRef *__restrict__ jobs,
 }
 
 // ---------------------------------------------------------------------------
-// Gram sums <u_j|u_l>, j <= l < K, one lattice per blockIdx.y; KM >= K is the
-// compile-time bound.  Each workgroup sums a fixed contiguous range of sites.
-// Runs on steps that orthogonalise (or when forced); `which` as for k_project.
+// Reflection projection of every projected state together with the Gram sums
+// <P u_j|P u_l>, j <= l < K, of all states (one lattice per blockIdx.y, KM >= K).
+// Used when all projected states reflect the same axes (proj_mode 1): sites are
+// taken in mirror pairs {s, R s}, each array is read and (if projected) written
+// once, and the Gram sums of the projected values come for free.  With
+// proj_mode 2 (different axes) the projections were done by k_project and this
+// kernel only sums; with `force` it sums the current arrays without projecting
+// (orthogonalisation on request).  Workgroup (plane x, chunk): planes are paired
+// with their mirror plane (the larger index contributes zeros).
 // ---------------------------------------------------------------------------
 template <typename R, int KM>
-__global__ void __launch_bounds__(NT) k_gram(const JobRef *__restrict__ lats, int force, int which) {
+__global__ void __launch_bounds__(NT) k_project_gram(const JobRef *__restrict__ lats, int force, int which) {
     constexpr int NG = MAXK * (MAXK + 1) / 2;
     constexpr int NGK = KM * (KM + 1) / 2;
     __shared__ double red[NGK * (NT / 64)];
     const LatDev &L = *lats[blockIdx.y].lat;
     const int K = L.nstates;
-    if (K < 2 || K > KM) return;
-    if (!force && (L.ortho_every <= 0 || ((L.step + 1) % L.ortho_every) != 0)) return;
-    const int n = L.n;
-    const size_t n3 = (size_t)n * n * n;
-    const size_t per = (n3 + gridDim.x - 1) / gridDim.x;
-    const size_t s0 = (size_t)blockIdx.x * per, s1 = s0 + per < n3 ? s0 + per : n3;
-    const R *uu[KM];
-#pragma unroll
-    for (int j = 0; j < KM; ++j) uu[j] = (const R *)state_buf(L, L.step, which, j < K ? j : 0);
+    const bool ortho = force || (K > 1 && L.ortho_every > 0 && ((L.step + 1) % L.ortho_every) == 0);
+    const bool do_proj = !force && L.proj_mode == 1;
+    if (!(ortho || (!force && L.proj_mode != 0)) || K > KM) return;  // finalize reads nothing then
+    const int n = L.n, center = L.center;
+    const int chunks = L.pg_chunks;
+    const int x = blockIdx.x / chunks, ch = blockIdx.x % chunks;
+    const int axes = do_proj ? L.proj_axes : 0;
+    const int xm = (axes & 1) ? mirror_idx(x, n, center) : x;
     double acc[NGK];
 #pragma unroll
     for (int g = 0; g < NGK; ++g) acc[g] = 0.0;
-    for (size_t s = s0 + threadIdx.x; s < s1; s += NT) {
-        double val[KM];
+    // threads along z (rows of n sites, NT / n rows at a time), rows [y0, y1) of plane x
+    const int rpi = NT / n;
+    const int z = threadIdx.x % n, ry = threadIdx.x / n;
+    if (xm >= x && ry < rpi) {
+        const size_t n2 = (size_t)n * n;
+        ITSE_GLOBAL R *ua[KM];
+        ITSE_GLOBAL R *ub[KM];
+        R sg[KM];
 #pragma unroll
-        for (int j = 0; j < KM; ++j) val[j] = j < K ? (double)uu[j][s] : 0.0;
-        int g = 0;
+        for (int j = 0; j < KM; ++j) {
+            ITSE_GLOBAL R *u = gmem((R *)state_buf(L, L.step, which, j < K ? j : 0));
+            ua[j] = u + (size_t)x * n2;
+            ub[j] = u + (size_t)xm * n2;
+            sg[j] = (do_proj && j < K) ? (R)L.psign[j] : (R)0;
+        }
+        const int rpc = (n + chunks - 1) / chunks;
+        const int y0 = ch * rpc, y1 = y0 + rpc < n ? y0 + rpc : n;
+        const int zm = (axes & 4) ? mirror_idx(z, n, center) : z;
+        // rows in batches of RB, the loads of the next batch issued before the stores
+        // of the current one (stores and loads share the memory wait counter)
+        constexpr int RB = 4;
+        const int nrows = y0 + ry < y1 ? (y1 - (y0 + ry) + rpi - 1) / rpi : 0;
+        const int nbatch = (nrows + RB - 1) / RB;
+        R ca[RB][KM], cb[RB][KM];
+        auto load_batch = [&](int bi, R (&la)[RB][KM], R (&lb)[RB][KM]) {
 #pragma unroll
-        for (int l = 0; l < KM; ++l)
+            for (int t = 0; t < RB; ++t) {
+                const int k = bi * RB + t;
+                const int y = y0 + ry + k * rpi;
+                const int ym = (axes & 2) ? mirror_idx(y, n, center) : y;
+                const bool ok = k < nrows;
+                const int e = ok ? y * n + z : 0, m = ok ? ym * n + zm : 0;
 #pragma unroll
-            for (int j = 0; j <= l; ++j) acc[g++] += val[j] * val[l];
+                for (int j = 0; j < KM; ++j) {
+                    la[t][j] = (ok && j < K) ? ua[j][e] : (R)0;
+                    lb[t][j] = (ok && j < K) ? ub[j][m] : (R)0;
+                }
+            }
+        };
+        if (nbatch > 0) load_batch(0, ca, cb);
+        for (int bi = 0; bi < nbatch; ++bi) {
+            R na[RB][KM], nb[RB][KM];
+            if (bi + 1 < nbatch) load_batch(bi + 1, na, nb);
+#pragma unroll
+            for (int t = 0; t < RB; ++t) {
+                const int k = bi * RB + t;
+                if (k >= nrows) continue;
+                const int y = y0 + ry + k * rpi;
+                const int ym = (axes & 2) ? mirror_idx(y, n, center) : y;
+                const int e = y * n + z, m = ym * n + zm;
+                const bool self = xm == x && m == e;
+                if (xm == x && m < e) continue;
+                double va[KM], vb[KM];
+#pragma unroll
+                for (int j = 0; j < KM; ++j) {
+                    va[j] = vb[j] = 0.0;
+                    if (j < K) {
+                        const R a = ca[t][j];
+                        const R b = self ? a : cb[t][j];
+                        R pa = a, pb = b;
+                        if (sg[j] != (R)0) {
+                            if (self) {
+                                pa = pb = sg[j] > (R)0 ? a : (R)0;
+                            } else {
+                                pa = (R)0.5 * (a + sg[j] * b);
+                                pb = sg[j] * pa;
+                            }
+                            ua[j][e] = pa;
+                            if (!self) ub[j][m] = pb;
+                        }
+                        va[j] = (double)pa;
+                        vb[j] = self ? 0.0 : (double)pb;
+                    }
+                }
+                int g = 0;
+#pragma unroll
+                for (int l = 0; l < KM; ++l)
+#pragma unroll
+                    for (int j = 0; j <= l; ++j) acc[g++] += va[j] * va[l] + vb[j] * vb[l];
+            }
+            if (bi + 1 < nbatch) {
+#pragma unroll
+                for (int t = 0; t < RB; ++t)
+#pragma unroll
+                    for (int j = 0; j < KM; ++j) {
+                        ca[t][j] = na[t][j];
+                        cb[t][j] = nb[t][j];
+                    }
+            }
+        }
     }
     // slot layout l (l + 1) / 2 + j, the same for every KM
     block_sums<NGK, NT>(acc, L.part_gram + (size_t)blockIdx.x * NG, red);

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "itse_internal.h"
+#include "itse_pass.h"
 #include "itse_runtime.h"
 
 using namespace itse;
@@ -54,70 +55,89 @@ extern "C" const char *itse_version(void) { return "itse 0.1 (gfx950)"; }
 // ------------------------------------------------------------------------------------
 namespace itse {
 
-constexpr int FIN_NT = 1024;
+constexpr int FIN_NT = 512;
+// Largest number of sums one lattice needs: rows and columns of every state, Gram.
+constexpr int FIN_QMAX = MAXK * (NQR + NQC) + MAXK * (MAXK + 1) / 2;
 
-// Fixed-order sum of count values p[b * stride] by the 16 lanes of a lane group:
-// lane l takes b = l, l + 16, ...; the 16 partial sums are combined by a fixed
-// butterfly.  Every lane of the group returns the total.
-__device__ __forceinline__ double group16_sum(const double *p, int count, int stride, int sub) {
-    double acc = 0.0;
-    for (int b = sub; b < count; b += 16) acc += p[(size_t)b * stride];
-#pragma unroll
-    for (int m = 8; m > 0; m >>= 1) acc += __shfl_xor(acc, m, 16);
-    return acc;
-}
-
+// Finalisation: workgroup (q, lattice) forms sum number q of the lattice from the
+// per-workgroup partials in a fixed order and stores it in the lattice record;
+// the last workgroup of the lattice to finish (counted with an atomic counter,
+// which it resets) forms the observables, the Gram-Schmidt coefficients and the
+// normalisation.  Results do not depend on which workgroup finishes last.
 __global__ void __launch_bounds__(FIN_NT) k_finalize(const JobRef *__restrict__ lats, int mode) {
     constexpr int NG = MAXK * (MAXK + 1) / 2;
-    __shared__ double rows[MAXK][NQR];
-    __shared__ double cols[MAXK][NQC];
-    __shared__ double proj[MAXK];
-    __shared__ double gram[NG];
-    LatDev &L = *lats[blockIdx.x].lat;
+    __shared__ double red[FIN_NT / 64];
+    __shared__ int last;
+    LatDev &L = *lats[blockIdx.y].lat;
     const int K = L.nstates;
     const bool ortho_step = (mode == FIN_STEP) && K > 1 && L.ortho_every > 0 &&
                             ((L.step + 1) % L.ortho_every) == 0;
-    // quantities: K*NQR row sums, K*NQC column sums (moments), K projection norms, Gram entries
+    // Gram sums of the updated (and projected) arrays exist on orthogonalisation steps
+    // and whenever states are projected (their diagonal then gives the norms)
+    const bool have_gram = (mode == FIN_STEP) && (ortho_step || L.proj_mode != 0);
+    // sums: K*NQR row sums, K*NQC column sums (moments), Gram entries
     const int q_rows = K * NQR;
     const int q_cols = L.moments ? K * NQC : 0;
-    const int q_proj = mode == FIN_STEP ? K : 0;
-    const int q_gram = ortho_step ? K * (K + 1) / 2 : 0;
-    const int total = q_rows + q_cols + q_proj + q_gram;
-    const int grp = threadIdx.x >> 4, sub = threadIdx.x & 15;
-    for (int q = grp; q < total; q += FIN_NT / 16) {
+    const int q_gram = have_gram ? K * (K + 1) / 2 : 0;
+    const int total = q_rows + q_cols + q_gram;
+    const int q = blockIdx.x;
+    if (q >= total) return;
+    {
         const double *p;
         int count, stride;
-        double *dst;
         if (q < q_rows) {
             const int i = q / NQR, c = q % NQR;
             p = L.part_rows + (size_t)i * L.nb_rows * NQR + c;
             count = L.nb_rows;
             stride = NQR;
-            dst = &rows[i][c];
         } else if (q < q_rows + q_cols) {
             const int t = q - q_rows, i = t / NQC, c = t % NQC;
             p = L.part_cols + (size_t)i * L.nb_cols * NQC + c;
             count = L.nb_cols;
             stride = NQC;
-            dst = &cols[i][c];
-        } else if (q < q_rows + q_cols + q_proj) {
-            const int i = q - q_rows - q_cols;
-            p = L.part_proj + (size_t)i * L.nb_proj;
-            count = L.psign[i] != 0 ? L.nb_proj : 0;  // no partials without a projection
-            stride = 1;
-            dst = &proj[i];
         } else {
-            const int slot = q - q_rows - q_cols - q_proj;  // l (l + 1) / 2 + j
+            const int slot = q - q_rows - q_cols;  // l (l + 1) / 2 + j
             p = L.part_gram + slot;
             count = L.nb_gram;
             stride = NG;
-            dst = &gram[slot];
         }
-        const double s = group16_sum(p, count, stride, sub);
-        if (sub == 0) *dst = s;
+        // up to 8 loads in flight per thread, added in a fixed order
+        double acc[1] = {0.0};
+        for (int b0 = 0; b0 < count; b0 += 8 * FIN_NT) {
+            double v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int b = b0 + t * FIN_NT + threadIdx.x;
+                v[t] = b < count ? p[(size_t)b * stride] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) acc[0] += v[t];
+        }
+        block_sums<1, FIN_NT>(acc, &L.fin_sums[q], red);
+    }
+    // the last workgroup of this lattice continues
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int done = atomicAdd(&L.fin_count, 1);
+        last = (done == total - 1);
     }
     __syncthreads();
+    if (!last) return;
+    // all sums of the lattice, read past the (non-coherent) L1 by one thread each
+    __shared__ double sums[FIN_QMAX];
+    if (threadIdx.x < total)
+        sums[threadIdx.x] = __hip_atomic_load(&L.fin_sums[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
     if (threadIdx.x != 0) return;
+    L.fin_count = 0;
+    double rows[MAXK][NQR];
+    double cols[MAXK][NQC];
+    double gram[NG];
+    for (int i = 0; i < K; ++i)
+        for (int c = 0; c < NQR; ++c) rows[i][c] = sums[i * NQR + c];
+    for (int i = 0; i < K; ++i)
+        for (int c = 0; c < NQC; ++c) cols[i][c] = q_cols ? sums[q_rows + i * NQC + c] : 0.0;
+    for (int g = 0; g < q_gram; ++g) gram[g] = sums[q_rows + q_cols + g];
     int err = 0;
     // observables of the states at the start of the step
     for (int i = 0; i < K; ++i) {
@@ -186,7 +206,7 @@ __global__ void __launch_bounds__(FIN_NT) k_finalize(const JobRef *__restrict__ 
     }
     if (!done) {
         for (int i = 0; i < K; ++i) {
-            const double nn = L.psign[i] != 0 ? proj[i] : rows[i][RQ_UU];
+            const double nn = have_gram ? gram[i * (i + 1) / 2 + i] : rows[i][RQ_UU];
             if (!(nn > 0.0) || !isfinite(nn)) err |= 1;
             M[i][i] = 1.0 / sqrt(nn);
         }
@@ -219,7 +239,7 @@ __global__ void __launch_bounds__(NT) k_check_potential(const LatDev *lp) {
 
 hipError_t launch_finalize(const JobRef *lats, int nlats, int mode, hipStream_t s) {
     if (nlats <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finalize, dim3(nlats), dim3(FIN_NT), 0, s, lats, mode);
+    hipLaunchKernelGGL(k_finalize, dim3(FIN_QMAX, nlats), dim3(FIN_NT), 0, s, lats, mode);
     return hipGetLastError();
 }
 
@@ -329,7 +349,7 @@ static hipError_t seq_step(const Group &g, hipStream_t s) {
     hipError_t e;
     if ((e = seq_forward_kin<R>(g, INV_UPDATE, s)) != hipSuccess) return e;
     if ((e = Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, 1, s)) != hipSuccess) return e;
-    if ((e = Launch<R>::gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s)) != hipSuccess) return e;
+    if ((e = Launch<R>::project_gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s)) != hipSuccess) return e;
     return launch_finalize(g.lats, g.nlats, FIN_STEP, s);
 }
 
@@ -459,7 +479,7 @@ extern "C" size_t itse_footprint_bytes(const itse_desc *d) {
     const size_t w = real_bytes(d->precision);
     const size_t n = (size_t)d->n, n3 = n * n * n;
     const size_t K = (size_t)std::max(1, std::min(d->nstates, MAXK));
-    const size_t spec = n * n * (n / 2 + 1) * 2 * w;
+    const size_t spec = spec_bytes(d->n, d->precision);
     size_t arena = 0;
     if (prec_supported(d->n, d->precision)) {
         const int nv = d->precision == ITSE_FP32 ? Launch<float>::variants(d->n) : Launch<double>::variants(d->n);
@@ -513,7 +533,7 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
     const int n = d->n, K = d->nstates;
     const size_t w = real_bytes(d->precision);
     const size_t n3 = (size_t)n * n * n;
-    const size_t spec = (size_t)n * n * (n / 2 + 1) * 2 * w;
+    const size_t spec = spec_bytes(n, d->precision);
     auto cleanup = [&](itse_status st) {
         lat_free_all(L);
         delete L;
@@ -543,6 +563,7 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
     H.nb_cols = L->sched.nb_cols;
     H.nb_proj = L->sched.nb_proj;
     H.nb_gram = L->sched.nb_gram;
+    H.pg_chunks = pg_chunks(n);
     H.part_rows = (double *)lat_alloc(L, (size_t)MAXK * H.nb_rows * NQR * 8);
     H.part_cols = (double *)lat_alloc(L, (size_t)MAXK * H.nb_cols * NQC * 8);
     H.part_proj = (double *)lat_alloc(L, (size_t)MAXK * H.nb_proj * 8);
@@ -735,10 +756,21 @@ extern "C" itse_status itse_set_step_opts(itse_lattice *L, const itse_step_opts 
     L->opts = *o;
     L->host.ortho_every = o->ortho_every;
     L->host.moments = o->moments ? 1 : 0;
+    int mode = 0, paxes = 0;
     for (int i = 0; i < MAXK; ++i) {
         L->host.psign[i] = i < L->d.nstates ? o->parity[i] : 0;
         L->host.paxes[i] = o->parity[i] ? o->axes[i] : 7;
+        if (L->host.psign[i] != 0) {
+            if (mode == 0) {
+                mode = 1;
+                paxes = L->host.paxes[i];
+            } else if (L->host.paxes[i] != paxes) {
+                mode = 2;
+            }
+        }
     }
+    L->host.proj_mode = mode;
+    L->host.proj_axes = paxes;
     return upload_opts(L);
 }
 
@@ -891,8 +923,9 @@ static double host_fixed_sum(const std::vector<double> &p, int count, int stride
 static itse_status gram_host(itse_lattice *L, double G[MAXK][MAXK]) {
     constexpr int NG = MAXK * (MAXK + 1) / 2;
     const int K = L->d.nstates;
-    hipError_t e = L->d.precision == ITSE_FP32 ? Launch<float>::gram(L->d.n, K, L->lat_dev, 1, 1, 0, L->stream)
-                                               : Launch<double>::gram(L->d.n, K, L->lat_dev, 1, 1, 0, L->stream);
+    hipError_t e = L->d.precision == ITSE_FP32
+                       ? Launch<float>::project_gram(L->d.n, K, L->lat_dev, 1, 1, 0, L->stream)
+                       : Launch<double>::project_gram(L->d.n, K, L->lat_dev, 1, 1, 0, L->stream);
     if (e != hipSuccess) return fail(ITSE_EDEVICE, "gram: %s", hipGetErrorString(e));
     std::vector<double> part((size_t)L->host.nb_gram * NG);
     HIPCHK(hipMemcpyAsync(part.data(), L->host.part_gram, part.size() * 8, hipMemcpyDeviceToHost, L->stream));
@@ -1057,11 +1090,12 @@ static hipError_t launch_pass(const Group &g, int p, hipStream_t s) {
     case 1: return Launch<R>::columns(g.n, g.variant, COL_KIN, 1, g.jobs, g.njobs, nullptr, s);
     case 2: return Launch<R>::plane_inv(g.n, g.variant, INV_UPDATE, g.jobs, g.njobs, s);
     case 3: return Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, 1, s);
-    case 4: return Launch<R>::gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s);
+    case 4: return Launch<R>::project_gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s);
     default: return launch_finalize(g.lats, g.nlats, FIN_STEP, s);
     }
 }
-static const char *pass_names[] = {"k_plane_fwd", "k_columns", "k_plane_inv", "k_project", "k_gram", "k_finalize"};
+static const char *pass_names[] = {"k_plane_fwd", "k_columns", "k_plane_inv", "k_project", "k_project_gram",
+                                   "k_finalize"};
 constexpr int NPASS = 6;
 }  // namespace itse
 

@@ -17,8 +17,8 @@ import synth
 pytestmark = pytest.mark.gpu
 
 CASES = [(48, "fp64", 0), (96, "fp64", 0), (128, "fp32", 0), (128, "fp32", 1), (128, "fp64", 0),
-         (192, "fp32", 0), (192, "fp64", 0), (256, "fp32", 0), (256, "fp32", 1), (256, "fp64", 0),
-         (256, "fp64", 1)]
+         (192, "fp32", 0), (192, "fp64", 0), (256, "fp32", 0), (256, "fp32", 1), (256, "fp32", 2),
+         (256, "fp64", 0), (256, "fp64", 1)]
 
 
 def _tol(prec):
@@ -100,6 +100,41 @@ def test_multistate_steps_large(itse, orc, n, prec, variant):
     for s in range(steps):
         for i in range(3):
             for f in ("energy", "norm2", "x", "r2", "parity_even"):
+                g, r = hist[s][i][f], ohist[s][i][f]
+                assert abs(g - r) <= etol * max(1.0, abs(r)), (s, i, f, g, r)
+    stol = 1e-10 if prec == "fp64" else 1e-4
+    for i in range(3):
+        assert _rel(lat.get_state(i), ostates[i]) < stol
+    lat.close()
+
+
+@pytest.mark.parametrize("n,prec,parity,axes,ortho", [
+    (24, "fp64", (1, -1, -1), (4, 2, 7), 1),     # three different reflections: projected one by one
+    (32, "fp64", (0, -1, 1), (7, 6, 6), 2),      # shared axes, Gram-Schmidt every other step
+    (32, "fp32", (1, 0, -1), (1, 7, 1), 3),
+    (24, "fp64", (-1, 1, 0), (7, 7, 7), 0),      # projections without Gram-Schmidt
+])
+def test_projection_modes(itse, orc, n, prec, parity, axes, ortho):
+    """Reflection projections with shared or different axes, with and without
+    Gram-Schmidt: energies and states follow the oracle."""
+    steps = 12
+    a = 0.2
+    lat = _lat(itse, n, prec, 0, kin=2, nstates=3, center="cell", a=a, mass=1.1)
+    dt = np.float32 if prec == "fp32" else np.float64
+    v = synth.potential_harmonic(n, a, "cell", 0.5).astype(dt)
+    states = synth.random_states(n, 3, seed=60, dtype=dt)
+    lat.set_potential(v)
+    for i, s in enumerate(states):
+        lat.set_state(i, s)
+    lat.set_options(ortho_every=ortho, moments=True, parity=parity, axes=axes)
+    lat.step(steps)
+    hist = lat.history(steps)
+    ostates, ohist = orc.step(_olat(orc, lat), [s.astype(np.float64) for s in states],
+                              v.astype(np.float64), steps, ortho_every=ortho, parity=parity, axes=axes)
+    etol = 1e-10 if prec == "fp64" else 1e-5
+    for s in range(steps):
+        for i in range(3):
+            for f in ("energy", "norm2", "z", "parity_even"):
                 g, r = hist[s][i][f], ohist[s][i][f]
                 assert abs(g - r) <= etol * max(1.0, abs(r)), (s, i, f, g, r)
     stol = 1e-10 if prec == "fp64" else 1e-4
