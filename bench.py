@@ -155,6 +155,20 @@ def main():
     lat.close()
 
     extra = {}
+    # the same lattice with one state and no projection or Gram-Schmidt: the bare
+    # three-pass step (32 + 32/N bytes per site in FP32)
+    import dataclasses
+    p1 = dataclasses.replace(p, nstates=1, parity=(0,))
+    lat1 = make_lattice(itse, p1, v32, st32[:1], fp32=True)
+    steps1 = max(20, args.steps // 2)
+    secs1 = timed_steps(torch, lat1, steps1, args.warmup)
+    prof1 = lat1.profile_step(args.profile_steps)
+    pb1 = pass_bytes(n, 4, 1, None, False)
+    extra["k1_site_steps_per_s"] = n ** 3 * steps1 / secs1
+    extra["k1_ms_per_step"] = secs1 * 1000.0 / steps1
+    extra["k1_hbm_frac"] = sum(pb1.values()) / (secs1 / steps1) / 1e9 / HBM_PEAK_GBS
+    extra["k1_passes_ms"] = prof1
+    lat1.close()
     if not args.no_fp64:
         p64, v64, st64 = build_workload(n, fp32=False)
         lat64 = make_lattice(itse, p64, v64, st64, fp32=False)

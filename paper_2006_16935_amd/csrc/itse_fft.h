@@ -233,9 +233,16 @@ __device__ __forceinline__ int padded(int e) {
     else return e + e / G;
 }
 
-template <typename R, int L, int P, int RAD, int LPW, int SIGN, bool LINE_FAST, int TWS, int GR, int GW>
+// No-op output hook of a transform stage.
+struct NoEpi {
+    template <typename V>
+    __device__ __forceinline__ void operator()(int, int, V &) const {}
+};
+
+template <typename R, int L, int P, int RAD, int LPW, int SIGN, bool LINE_FAST, int TWS, int GR, int GW,
+          class Epi = NoEpi>
 __device__ __forceinline__ void wave_stage(C2<R> *__restrict__ buf, int LS, int ES,
-                                           const C2<R> *__restrict__ tw, int lane) {
+                                           const C2<R> *__restrict__ tw, int lane, Epi &&epi = Epi{}) {
     constexpr int B = L / RAD;
     constexpr int TASKS = LPW * B;
     constexpr int TPT = (TASKS + 63) / 64;
@@ -271,7 +278,11 @@ __device__ __forceinline__ void wave_stage(C2<R> *__restrict__ buf, int LS, int 
             const int k = j % P;
             C2<R> *b = buf + line * LS;
 #pragma unroll
-            for (int q = 0; q < RAD; ++q) b[padded<GW>((j - k) * RAD + k + q * P) * ES] = v[t][q];
+            for (int q = 0; q < RAD; ++q) {
+                const int e = (j - k) * RAD + k + q * P;
+                epi(line, e, v[t][q]);  // output e of local line `line` (final stage: frequency e)
+                b[padded<GW>(e) * ES] = v[t][q];
+            }
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -287,19 +298,30 @@ struct WaveFft {
     static constexpr int R1 = stage_radix(L);
     static constexpr bool PAD2 = !LINE_FAST && num_stages(L) == 2;
     static constexpr int SPAN = PAD2 ? L + L / R1 : L;  // slots a line needs
-    template <int P>
-    static __device__ __forceinline__ void from(C2<R> *buf, int LS, int ES, const C2<R> *tw, int lane) {
+    template <int P, class Epi>
+    static __device__ __forceinline__ void from(C2<R> *buf, int LS, int ES, const C2<R> *tw, int lane, Epi &epi) {
         if constexpr (P < L) {
             constexpr int RAD = stage_radix(L / P);
             static_assert(RAD > 1, "length must factor into 2, 3");
             constexpr int GR = (PAD2 && P > 1) ? R1 : 0;
             constexpr int GW = (PAD2 && P == 1) ? R1 : 0;
-            wave_stage<R, L, P, RAD, LPW, SIGN, LINE_FAST, TWS, GR, GW>(buf, LS, ES, tw, lane);
-            from<P * RAD>(buf, LS, ES, tw, lane);
+            if constexpr (P * RAD == L)
+                wave_stage<R, L, P, RAD, LPW, SIGN, LINE_FAST, TWS, GR, GW>(buf, LS, ES, tw, lane, epi);
+            else
+                wave_stage<R, L, P, RAD, LPW, SIGN, LINE_FAST, TWS, GR, GW>(buf, LS, ES, tw, lane);
+            from<P * RAD>(buf, LS, ES, tw, lane, epi);
         }
     }
     static __device__ __forceinline__ void run(C2<R> *buf, int LS, int ES, const C2<R> *tw, int lane) {
-        from<1>(buf, LS, ES, tw, lane);
+        NoEpi none;
+        from<1>(buf, LS, ES, tw, lane, none);
+    }
+    // Same, with epi(line, k, value) applied to every output of the final stage
+    // (value k of local line `line`, natural order) before it is stored.
+    template <class Epi>
+    static __device__ __forceinline__ void run_epi(C2<R> *buf, int LS, int ES, const C2<R> *tw, int lane,
+                                                   Epi &epi) {
+        from<1>(buf, LS, ES, tw, lane, epi);
     }
 };
 

@@ -141,7 +141,12 @@ struct Geo {
     static constexpr int LINES = S * W;              // x lines per column workgroup
     static_assert(LINES % NWC == 0, "lines split evenly over waves");
     static constexpr int LPWC = LINES / NWC;
-    static constexpr int CS = LINES + 1;  // row stride (x) in the column layout
+    // Row stride (x) of the column layout, = 4 (mod 32) complex FP32 values or
+    // = 4 (mod 16) FP64 ones: rows then start 8 (16) banks apart, which spreads both
+    // the butterfly accesses (a few lines x 16 rows) and the row-wise load/store
+    // accesses over all banks.
+    static constexpr int CSMOD = sizeof(R) == 4 ? 32 : 16;
+    static constexpr int CS = LINES + ((4 - LINES % CSMOD) + CSMOD) % CSMOD;
     static constexpr int NTC = 64 * NWC;
     static constexpr int NB_PLANE = N * S;           // plane workgroups per state
     static constexpr int NB_COLS = M * NCH;          // column workgroups per state
@@ -467,8 +472,8 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTC)) k_columns(const JobRef *_
     }
     __syncthreads();
     const int l0 = wv * LPW;
-    WaveFft<R, N, LPW, -1, true, 1>::run(buf + l0, 1, CS, tw, lane);
     if (mode == COL_FWD) {
+        WaveFft<R, N, LPW, -1, true, 1>::run(buf + l0, 1, CS, tw, lane);
         __syncthreads();
         for (int e = tid; e < N * S * W; e += NTC) {
             const int xx = e / (S * W), l = e % (S * W), q = l / W, w = l % W, kz = kz0 + w;
@@ -476,15 +481,17 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTC)) k_columns(const JobRef *_
         }
         return;
     }
-    // kinetic multiply on this wave's lines: T(kx, ky, kz) / N^3 in FP64
+    // forward transform along x with the kinetic multiply T(kx, ky, kz) / N^3 (FP64
+    // symbol and product) applied to its final outputs
     const double inv_n3 = 1.0 / ((double)N * (double)N * (double)N);
     const bool mom = moments && L.moments;
+    const int kin = L.kin, rest = L.sub, center = L.center;
+    const double mass = L.mass;
     double acc[NQC] = {0.0, 0.0};
-    for (int e = lane; e < N * LPW; e += 64) {
-        const int xx = e / LPW, l = l0 + e % LPW, q = l / W, kz = kz0 + l % W;
-        if (kz >= H) continue;
+    auto kinetic = [&](int line, int kx, C2<R> &val) {
+        const int l = l0 + line, q = l / W, kz = kz0 + l % W;
+        if (kz >= H) return;
         const int ky = kyp + M * q;
-        C2<R> val = buf[xx * CS + l];
         if (mom) {
             // weight 2 for the interior of the half spectrum (its mirror is implied)
             const double wt = (kz == 0 || 2 * kz == N) ? 1.0 : 2.0;
@@ -494,19 +501,19 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTC)) k_columns(const JobRef *_
             // for the off-grid centre (x -> N-1-x), kappa = 0 for the origin
             double pr = re * re - im * im;
             const double pim = -2.0 * re * im;
-            if (L.center == ITSE_CENTER_CELL) {
-                const int mm = (xx + ky + kz) % N;
+            if (center == ITSE_CENTER_CELL) {
+                const int mm = (kx + ky + kz) % N;
                 double sn, cs;
                 sincospi(2.0 * (double)mm / (double)N, &sn, &cs);
                 pr = cs * pr - sn * pim;
             }
             acc[CQ_PAR] += wt * pr;
         }
-        const double t = kin_symbol(L.kin, L.sub, L.mass, ktab[xx] + ktab[ky] + ktab[kz]) * inv_n3;
+        const double t = kin_symbol(kin, rest, mass, ktab[kx] + ktab[ky] + ktab[kz]) * inv_n3;
         val.x = (R)((double)val.x * t);
         val.y = (R)((double)val.y * t);
-        buf[xx * CS + l] = val;
-    }
+    };
+    WaveFft<R, N, LPW, -1, true, 1>::run_epi(buf + l0, 1, CS, tw, lane, kinetic);
     __builtin_amdgcn_wave_barrier();
     WaveFft<R, N, LPW, +1, true, 1>::run(buf + l0, 1, CS, tw, lane);
     if (mom) block_sums<NQC, NTC>(acc, L.part_cols + ((size_t)i * L.nb_cols + blk) * NQC, red);

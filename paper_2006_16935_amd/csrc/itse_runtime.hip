@@ -130,9 +130,13 @@ __global__ void __launch_bounds__(FIN_NT) k_finalize(const JobRef *__restrict__ 
     __syncthreads();
     if (threadIdx.x != 0) return;
     L.fin_count = 0;
-    double rows[MAXK][NQR];
-    double cols[MAXK][NQC];
-    double gram[NG];
+    // the serial tail works in LDS (per-thread arrays indexed by the runtime state
+    // count would live in scratch memory)
+    __shared__ double rows[MAXK][NQR];
+    __shared__ double cols[MAXK][NQC];
+    __shared__ double gram[NG];
+    __shared__ double M[MAXK][MAXK];
+    __shared__ double Rm[MAXK][MAXK];
     for (int i = 0; i < K; ++i)
         for (int c = 0; c < NQR; ++c) rows[i][c] = sums[i * NQR + c];
     for (int i = 0; i < K; ++i)
@@ -167,13 +171,11 @@ __global__ void __launch_bounds__(FIN_NT) k_finalize(const JobRef *__restrict__ 
         return;
     }
     // coefficients of the new states in terms of the raw updated arrays
-    double M[MAXK][MAXK];
     for (int j = 0; j < MAXK; ++j)
         for (int i = 0; i < MAXK; ++i) M[j][i] = 0.0;
     bool done = false;
     if (ortho_step) {
         // G = R^T R (R upper); new states = U R^{-1}
-        double Rm[MAXK][MAXK];
         bool ok = true;
         for (int j = 0; j < K && ok; ++j) {
             for (int i = j; i < K; ++i) {
