@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=5)
+    ap.add_argument("--schedule", type=int, default=-1,
+                    help="schedule variant for the 256^3 FP32 lattice (default: autotune)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 256 MiB five times (scale for HBM counters)")
     args = ap.parse_args()
@@ -135,7 +137,11 @@ def main():
     n = args.n
     # schedule per (n, precision) picked by the library's autotuner (timed outside the
     # measured region; results are deterministic for a given schedule)
-    tune32 = json.loads(itse.autotune(n, "fp32"))
+    if args.schedule >= 0:
+        itse.set_schedule(n, "fp32", args.schedule)
+        tune32 = None
+    else:
+        tune32 = json.loads(itse.autotune(n, "fp32"))
     tune64 = None if args.no_fp64 else json.loads(itse.autotune(n, "fp64"))
     p, v32, st32 = build_workload(n, fp32=True)
     lat = make_lattice(itse, p, v32, st32, fp32=True)

@@ -214,9 +214,8 @@ constexpr int num_stages(int L) {
 // ---------------------------------------------------------------------------
 // One Stockham (autosort, decimation in time) stage of radix RAD over LPW lines
 // of length L owned by the calling wavefront.  P = product of the radices
-// already applied.  Element e of local line l is at buf[l*LS + pad(e)*ES], where
-// pad(e) = e + e / G inserts one gap after every G elements (G = 0: no gaps);
-// GR applies to the reads of this stage, GW to its writes.  Butterfly j
+// already applied.  Element e of local line l is at buf[l*LS + padded(e)*ES], with
+// layout MR for the reads of this stage and MW for its writes (see padded()).  Butterfly j
 // (< L/RAD) reads x[j + m L/RAD] (m < RAD), twiddles input m by
 // w_L^(k m L/(P RAD)) with k = j mod P, and writes output q to
 // (j - k) RAD + k + q P.  Twiddles come from tw[] = w_N^e (N = L * TWS), with
@@ -227,10 +226,25 @@ constexpr int num_stages(int L) {
 // are in registers), and no other wavefront touches these lines, so no
 // workgroup barrier is needed.
 // ---------------------------------------------------------------------------
-template <int G>
+// Slot of element e in the layout between the two stages of a two-stage
+// transform with first radix G (e = hi G + lo, lo < G):
+//  MODE 0: natural, slot e;
+//  MODE 1: one gap after every G elements, slot e + hi (contiguous lines);
+//  MODE 2: lo rotated by hi, slot hi G + (lo + hi) mod G (element-strided lines:
+//          the first stage's writes, at fixed lo and hi varying over the lanes,
+//          and the second stage's reads, at fixed hi and lo varying, both fall on
+//          distinct rows mod G, hence on different banks; no extra storage).
+template <int MODE, int G>
 __device__ __forceinline__ int padded(int e) {
-    if constexpr (G == 0) return e;
-    else return e + e / G;
+    if constexpr (MODE == 0) {
+        return e;
+    } else if constexpr (MODE == 1) {
+        return e + e / G;
+    } else {
+        const int hi = e / G, lo = e - hi * G;
+        const int r = lo + hi % G;
+        return hi * G + (r >= G ? r - G : r);
+    }
 }
 
 // No-op output hook of a transform stage.
@@ -239,7 +253,7 @@ struct NoEpi {
     __device__ __forceinline__ void operator()(int, int, V &) const {}
 };
 
-template <typename R, int L, int P, int RAD, int LPW, int SIGN, bool LINE_FAST, int TWS, int GR, int GW,
+template <typename R, int L, int P, int RAD, int LPW, int SIGN, bool LINE_FAST, int TWS, int MR, int MW, int G,
           class Epi = NoEpi>
 __device__ __forceinline__ void wave_stage(C2<R> *__restrict__ buf, int LS, int ES,
                                            const C2<R> *__restrict__ tw, int lane, Epi &&epi = Epi{}) {
@@ -257,7 +271,7 @@ __device__ __forceinline__ void wave_stage(C2<R> *__restrict__ buf, int LS, int 
             const C2<R> *b = buf + line * LS;
 #pragma unroll
             for (int m = 0; m < RAD; ++m) {
-                C2<R> a = b[padded<GR>(j + m * B) * ES];
+                C2<R> a = b[padded<MR, G>(j + m * B) * ES];
                 if (P > 1 && m > 0) {
                     C2<R> w = tw[(k * m * (L / (P * RAD))) * TWS];
                     if (SIGN > 0) w.y = -w.y;
@@ -281,34 +295,35 @@ __device__ __forceinline__ void wave_stage(C2<R> *__restrict__ buf, int LS, int 
             for (int q = 0; q < RAD; ++q) {
                 const int e = (j - k) * RAD + k + q * P;
                 epi(line, e, v[t][q]);  // output e of local line `line` (final stage: frequency e)
-                b[padded<GW>(e) * ES] = v[t][q];
+                b[padded<MW, G>(e) * ES] = v[t][q];
             }
         }
     }
     __builtin_amdgcn_wave_barrier();
 }
 
-// Whole transform: successive stages from P = 1.  For a two-stage plan on a
-// contiguous line (ES = 1, lanes along the line) the intermediate layout gets
-// one gap per RAD1 elements, which turns the first stage's stride-RAD1 writes
-// into bank-conflict-free ones; the line then needs L + L/RAD1 slots.  Input and
-// output are in natural order without gaps.
+// Whole transform: successive stages from P = 1.  For a two-stage plan the
+// intermediate layout is changed so that the first stage's stride-RAD1 writes do
+// not fall on one bank: one gap per RAD1 elements on contiguous lines (the line
+// then needs L + L/RAD1 slots), a rotation on element-strided lines.  Input and
+// output are in natural order.
 template <typename R, int L, int LPW, int SIGN, bool LINE_FAST, int TWS>
 struct WaveFft {
     static constexpr int R1 = stage_radix(L);
-    static constexpr bool PAD2 = !LINE_FAST && num_stages(L) == 2;
-    static constexpr int SPAN = PAD2 ? L + L / R1 : L;  // slots a line needs
+    static constexpr bool TWO = num_stages(L) == 2;
+    static constexpr int MODE = !TWO ? 0 : (LINE_FAST ? 2 : 1);   // intermediate layout
+    static constexpr int SPAN = MODE == 1 ? L + L / R1 : L;       // slots a line needs
     template <int P, class Epi>
     static __device__ __forceinline__ void from(C2<R> *buf, int LS, int ES, const C2<R> *tw, int lane, Epi &epi) {
         if constexpr (P < L) {
             constexpr int RAD = stage_radix(L / P);
             static_assert(RAD > 1, "length must factor into 2, 3");
-            constexpr int GR = (PAD2 && P > 1) ? R1 : 0;
-            constexpr int GW = (PAD2 && P == 1) ? R1 : 0;
+            constexpr int MR = (TWO && P > 1) ? MODE : 0;
+            constexpr int MW = (TWO && P == 1) ? MODE : 0;
             if constexpr (P * RAD == L)
-                wave_stage<R, L, P, RAD, LPW, SIGN, LINE_FAST, TWS, GR, GW>(buf, LS, ES, tw, lane, epi);
+                wave_stage<R, L, P, RAD, LPW, SIGN, LINE_FAST, TWS, MR, MW, R1>(buf, LS, ES, tw, lane, epi);
             else
-                wave_stage<R, L, P, RAD, LPW, SIGN, LINE_FAST, TWS, GR, GW>(buf, LS, ES, tw, lane);
+                wave_stage<R, L, P, RAD, LPW, SIGN, LINE_FAST, TWS, MR, MW, R1>(buf, LS, ES, tw, lane);
             from<P * RAD>(buf, LS, ES, tw, lane, epi);
         }
     }

@@ -18,7 +18,7 @@ struct NVariants<float, 128> {
 };
 template <>
 struct NVariants<float, 256> {
-    static constexpr int value = 3;
+    static constexpr int value = 4;
 };
 template <>
 struct NVariants<double, 256> {
@@ -53,6 +53,8 @@ static hipError_t dispatch(int n, int variant, F f) {
             if (variant == 1) return f.template operator()<NN, 1>();                   \
         if constexpr (NVariants<R, NN>::value > 2)                                     \
             if (variant == 2) return f.template operator()<NN, 2>();                   \
+        if constexpr (NVariants<R, NN>::value > 3)                                     \
+            if (variant == 3) return f.template operator()<NN, 3>();                   \
         return hipErrorInvalidValue;
         ITSE_FOR_EACH_N(ITSE_CASE)
 #undef ITSE_CASE

@@ -90,6 +90,7 @@ ITSE_PLAN(float, 192, 0, 2, 8, 16, 8)
 ITSE_PLAN(float, 256, 0, 4, 8, 16, 16)
 ITSE_PLAN(float, 256, 1, 2, 8, 16, 8)
 ITSE_PLAN(float, 256, 2, 4, 8, 8, 8)
+ITSE_PLAN(float, 256, 3, 4, 8, 4, 4)
 // FP64
 ITSE_PLAN(double, 8, 0, 1, 1, 5, 1)
 ITSE_PLAN(double, 12, 0, 1, 1, 7, 1)
