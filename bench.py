@@ -101,6 +101,82 @@ def cpu_baseline(p, v, states, budget_s: float = 30.0):
             "sample": f"1 step of all {p.nstates} states of the {p.n}^3 workload in FP64 ({dt:.1f} s)"}
 
 
+def batch_leg(torch, itse, steps: int, warmup: int, count: int = 64):
+    """The batched form: `count` independent solves (N in {32, 48, 64, 96}, masses,
+    Cornell couplings and kinetic terms drawn by synth.batch_problems), two states
+    each, FP32 with FP64 sums, stepped together; aggregate site-steps/s."""
+    import synth
+    probs = synth.batch_problems(count=count, seed=0, nstates=2)
+    lats = []
+    for p in probs:
+        lat = itse.Lattice(p.n, p.a, p.mass, p.dtau, kin=p.kin, subtract_rest_mass=p.subtract_rest_mass,
+                           precision="fp32", center=p.center, nstates=p.nstates)
+        lat.set_potential(p.potential_array(np.float64).astype(np.float32))
+        for i, st in enumerate(p.initial_states(np.float32)):
+            lat.set_state(i, st)
+        lat.set_options(ortho_every=1)
+        lats.append(lat)
+    b = itse.Batch(lats)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(b.stream)
+    b.step(steps)
+    stop.record(b.stream)
+    torch.cuda.synchronize()
+    secs = start.elapsed_time(stop) / 1000.0
+    for lat in lats:
+        lat.sync()
+    sites = sum(p.n ** 3 * p.nstates for p in probs)
+    sizes = {}
+    for p in probs:
+        sizes[p.n] = sizes.get(p.n, 0) + 1
+    b.close()
+    for lat in lats:
+        lat.close()
+    return {"site_steps_per_s": sites * steps / secs, "ms_per_step": secs * 1000.0 / steps,
+            "lattices": count, "sizes": sizes, "steps": steps, "site_steps_per_step": sites}
+
+
+def serving_run(torch, itse, count: int, qps: float, budget: int, seed: int = 1):
+    """The serving form: `count` requests arriving as a Poisson stream at `qps`
+    (synth.serving_requests: N in {64, 128, 192, 256}, two states, relative tolerance
+    1e-8), admitted by footprint against `budget` bytes; latency = arrival to result."""
+    import time as _time
+    import synth
+    reqs = synth.serving_requests(count, qps, seed=seed)
+    server = itse.Server(hbm_budget=budget, max_slots=64, chunk=100)
+    t0 = _time.perf_counter()
+    nxt = 0
+    arrival, done, ids = {}, {}, {}
+    site_steps = 0
+    while len(done) < count:
+        now = _time.perf_counter() - t0
+        while nxt < count and reqs[nxt][0] <= now:
+            t_arr, p = reqs[nxt]
+            rid = server.submit(p.n, p.a, p.mass, p.dtau, p.potential_array(np.float64).astype(np.float32),
+                                p.initial_states(np.float32), kin=p.kin,
+                                subtract_rest_mass=p.subtract_rest_mass, precision="fp32", center=p.center,
+                                ortho_every=1, tol=p.tol, relative=True, max_steps=60000)
+            arrival[rid] = t_arr
+            ids[rid] = p
+            nxt += 1
+        live, queued = server.progress()
+        for r in server.poll():
+            done[r["id"]] = (_time.perf_counter() - t0, r)
+            site_steps += ids[r["id"]].n ** 3 * ids[r["id"]].nstates * r["steps"]
+        if live == 0 and queued == 0 and nxt < count:
+            _time.sleep(max(0.0, reqs[nxt][0] - (_time.perf_counter() - t0)))
+    wall = _time.perf_counter() - t0
+    server.close()
+    lat = np.array([done[i][0] - arrival[i] for i in done])
+    conv = sum(1 for i in done if done[i][1]["converged"])
+    return {"requests": count, "qps": qps, "budget_bytes": budget, "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)), "mean_latency_s": float(lat.mean()),
+            "site_steps_per_s": site_steps / wall, "wall_s": wall, "converged": conv,
+            "steps_mean": float(np.mean([done[i][1]["steps"] for i in done]))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +188,12 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=5)
     ap.add_argument("--schedule", type=int, default=-1,
                     help="schedule variant for the 256^3 FP32 lattice (default: autotune)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-lattice batched leg")
+    ap.add_argument("--serving", action="store_true",
+                    help="only run the serving form (Poisson arrivals) and print its JSON line")
+    ap.add_argument("--requests", type=int, default=24)
+    ap.add_argument("--qps", type=float, default=4.0)
+    ap.add_argument("--budget-gb", type=float, default=288.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 256 MiB five times (scale for HBM counters)")
     args = ap.parse_args()
@@ -134,6 +216,10 @@ def main():
     import paper_2006_16935_amd as itse
 
     torch.cuda.set_device(0)
+    if args.serving:
+        res = serving_run(torch, itse, args.requests, args.qps, int(args.budget_gb * (1 << 30)))
+        print(json.dumps({"metric": "p50/p99 solve latency, serving form", **res}), flush=True)
+        return
     n = args.n
     # schedule per (n, precision) picked by the library's autotuner (timed outside the
     # measured region; results are deterministic for a given schedule)
@@ -211,6 +297,8 @@ def main():
         "step_hbm_frac": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "energies_fp32": e_fp32,
     }
+    if not args.no_batch:
+        extra["batch64"] = batch_leg(torch, itse, max(20, args.steps // 2), 5)
     out.update(extra)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, v32.astype(np.float64), [s.astype(np.float64) for s in st32])

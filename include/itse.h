@@ -220,6 +220,62 @@ itse_status itse_autotune(int n, int precision, void *hip_stream, char *json, si
 itse_status itse_schedule_get(int n, int precision, char *json, size_t json_len);
 itse_status itse_schedule_set(int n, int precision, int variant);
 
+/* ---- serving: eigensolve requests with admission by HBM footprint ---------------- */
+/* A server owns the lattices of the requests it has admitted.  Requests wait in
+ * arrival order until their footprint (itse_footprint_bytes) fits the server's
+ * HBM budget beside the admitted ones and a slot is free; admitted requests are
+ * stepped together (continuous batching: all live lattices advance by one chunk
+ * of steps per itse_server_progress call, each in its own arrays, so a request's
+ * results do not depend on what else is live).  After every chunk each request
+ * compares its energies with those one chunk earlier (the paper's tolerance test,
+ * section "Basic configuration", on |dE|) and completes when every state moved by
+ * at most tol (relative to |E| when tol_relative), or at max_steps.  The calls are
+ * not thread-safe: one host thread drives a server. */
+typedef struct {
+    itse_desc desc;              /* lattice, kinetic term, precision, states          */
+    const void *potential;       /* host, N^3 values of potential_dtype               */
+    int potential_dtype;         /* itse_dtype                                        */
+    const void *const *states;   /* host, desc.nstates arrays of state_dtype          */
+    int state_dtype;             /* itse_dtype                                        */
+    itse_step_opts opts;         /* projections and Gram-Schmidt interval             */
+    double tol;                  /* energy change per chunk that counts as converged  */
+    int tol_relative;            /* 1: tol relative to |E|                            */
+    int keep_states;             /* 1: keep the final states for itse_server_state    */
+    long long max_steps;         /* give up after this many steps (converged = 0)     */
+} itse_request;
+
+typedef struct {
+    uint64_t id;                 /* as returned by itse_server_submit                 */
+    int status;                  /* itse_status of the solve                          */
+    int converged;               /* 1 if the tolerance was met                        */
+    long long steps;             /* steps taken                                       */
+    double energy[ITSE_MAX_STATES];  /* final energies (FP64 sums)                   */
+    double t_submit, t_admit, t_done;  /* seconds on the server's clock               */
+} itse_result;
+
+/* hbm_budget: device bytes the admitted lattices may hold in total; max_slots:
+ * most requests live at once; chunk: steps per itse_server_progress.  Work runs
+ * on hip_stream (may be NULL). */
+itse_status itse_server_create(size_t hbm_budget, int max_slots, int chunk, void *hip_stream,
+                               itse_server **out);
+itse_status itse_server_destroy(itse_server *s);
+/* Copies the request's host arrays (they may be freed on return).  Rejects a
+ * request whose footprint alone exceeds the budget (ITSE_ENOMEM) and invalid
+ * descriptions (ITSE_EINVAL, ITSE_EUNSTABLE) at once. */
+itse_status itse_server_submit(itse_server *s, const itse_request *req, uint64_t *id);
+/* Admit what fits, step every live request by one chunk, test convergence,
+ * retire finished requests (freeing their device memory).  *live and *queued
+ * (optional) receive the counts after the call.  Synchronises the stream. */
+itse_status itse_server_progress(itse_server *s, int *live, int *queued);
+/* Up to max finished results, oldest first; *n_out receives the count. */
+itse_status itse_server_poll(itse_server *s, itse_result *out, int max, int *n_out);
+/* Final state i of a finished request submitted with keep_states, as N^3 values of
+ * dtype into host memory; itse_server_release drops the kept states. */
+itse_status itse_server_state(itse_server *s, uint64_t id, int i, void *out, int dtype);
+itse_status itse_server_release(itse_server *s, uint64_t id);
+/* Device bytes currently held by admitted requests. */
+size_t itse_server_bytes_in_use(const itse_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -49,6 +49,19 @@ class StepOpts(ctypes.Structure):
                 ("parity", ctypes.c_int * MAX_STATES), ("axes", ctypes.c_int * MAX_STATES)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("desc", Desc), ("potential", ctypes.c_void_p), ("potential_dtype", ctypes.c_int),
+                ("states", ctypes.POINTER(ctypes.c_void_p)), ("state_dtype", ctypes.c_int),
+                ("opts", StepOpts), ("tol", ctypes.c_double), ("tol_relative", ctypes.c_int),
+                ("keep_states", ctypes.c_int), ("max_steps", ctypes.c_longlong)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("status", ctypes.c_int), ("converged", ctypes.c_int),
+                ("steps", ctypes.c_longlong), ("energy", ctypes.c_double * MAX_STATES),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 
@@ -100,6 +113,14 @@ def load():
         "itse_autotune": ([ip, ip, vp, ctypes.c_char_p, ctypes.c_size_t], ip),
         "itse_schedule_get": ([ip, ip, ctypes.c_char_p, ctypes.c_size_t], ip),
         "itse_schedule_set": ([ip, ip, ip], ip),
+        "itse_server_create": ([ctypes.c_size_t, ip, ip, vp, P(vp)], ip),
+        "itse_server_destroy": ([vp], ip),
+        "itse_server_submit": ([vp, P(Request), P(ctypes.c_uint64)], ip),
+        "itse_server_progress": ([vp, P(ip), P(ip)], ip),
+        "itse_server_poll": ([vp, P(Result), ip, P(ip)], ip),
+        "itse_server_state": ([vp, ctypes.c_uint64, ip, vp, ip], ip),
+        "itse_server_release": ([vp, ctypes.c_uint64], ip),
+        "itse_server_bytes_in_use": ([vp], ctypes.c_size_t),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)

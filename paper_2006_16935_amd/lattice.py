@@ -291,3 +291,72 @@ def set_schedule(n: int, precision: str, variant: int):
 def schedule_variants(n: int, precision: str = "fp32") -> int:
     import json
     return int(json.loads(schedule(n, precision))["variants"])
+
+
+class Server:
+    """Eigensolve requests admitted by HBM footprint and stepped together
+    (continuous batching).  Thin wrapper of the itse_server_* calls."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 64, chunk: int = 100, stream=None):
+        self._L = _lib.load()
+        self._stream_ptr, self.stream = _stream_handle(stream)
+        handle = ctypes.c_void_p()
+        check(self._L.itse_server_create(int(hbm_budget), int(max_slots), int(chunk), self._stream_ptr,
+                                         ctypes.byref(handle)))
+        self.h = handle
+
+    def submit(self, n, a, mass, dtau, potential, states, kin=_lib.KIN_REL_LAT, subtract_rest_mass=True,
+               precision="fp32", center="origin", parity=None, axes=None, ortho_every=1, tol=1e-8,
+               relative=True, keep_states=False, max_steps=100000) -> int:
+        pot = np.ascontiguousarray(potential)
+        sts = [np.ascontiguousarray(s) for s in states]
+        desc = _lib.Desc(int(n), float(a), float(mass), float(dtau), int(kin), 1 if subtract_rest_mass else 0,
+                         _PREC[precision], _CENTER[center], len(sts))
+        ptrs = (ctypes.c_void_p * len(sts))(*[s.ctypes.data for s in sts])
+        req = _lib.Request(desc, pot.ctypes.data, _dtype_code(pot), ptrs, _dtype_code(sts[0]),
+                           make_opts(len(sts), ortho_every, False, parity, axes), float(tol),
+                           1 if relative else 0, 1 if keep_states else 0, int(max_steps))
+        rid = ctypes.c_uint64()
+        check(self._L.itse_server_submit(self.h, ctypes.byref(req), ctypes.byref(rid)))
+        return int(rid.value)
+
+    def progress(self):
+        live, queued = ctypes.c_int(), ctypes.c_int()
+        check(self._L.itse_server_progress(self.h, ctypes.byref(live), ctypes.byref(queued)))
+        return live.value, queued.value
+
+    def poll(self, max_results: int = 256):
+        buf = (_lib.Result * max_results)()
+        n = ctypes.c_int()
+        check(self._L.itse_server_poll(self.h, buf, int(max_results), ctypes.byref(n)))
+        out = []
+        for r in buf[: n.value]:
+            out.append({"id": int(r.id), "status": int(r.status), "converged": bool(r.converged),
+                        "steps": int(r.steps), "energy": list(r.energy), "t_submit": r.t_submit,
+                        "t_admit": r.t_admit, "t_done": r.t_done})
+        return out
+
+    def state(self, rid: int, i: int, n: int, dtype=np.float64):
+        out = np.empty((n, n, n), dtype=dtype)
+        code = _lib.DTYPE_F32 if out.dtype == np.float32 else _lib.DTYPE_F64
+        check(self._L.itse_server_state(self.h, ctypes.c_uint64(rid), int(i),
+                                        out.ctypes.data_as(ctypes.c_void_p), code))
+        return out
+
+    def release(self, rid: int):
+        check(self._L.itse_server_release(self.h, ctypes.c_uint64(rid)))
+
+    @property
+    def bytes_in_use(self) -> int:
+        return int(self._L.itse_server_bytes_in_use(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.itse_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
