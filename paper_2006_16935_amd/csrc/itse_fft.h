@@ -247,16 +247,9 @@ __device__ __forceinline__ int padded(int e) {
     }
 }
 
-// No-op output hook of a transform stage.
-struct NoEpi {
-    template <typename V>
-    __device__ __forceinline__ void operator()(int, int, V &) const {}
-};
-
-template <typename R, int L, int P, int RAD, int LPW, int SIGN, bool LINE_FAST, int TWS, int MR, int MW, int G,
-          class Epi = NoEpi>
+template <typename R, int L, int P, int RAD, int LPW, int SIGN, bool LINE_FAST, int TWS, int MR, int MW, int G>
 __device__ __forceinline__ void wave_stage(C2<R> *__restrict__ buf, int LS, int ES,
-                                           const C2<R> *__restrict__ tw, int lane, Epi &&epi = Epi{}) {
+                                           const C2<R> *__restrict__ tw, int lane) {
     constexpr int B = L / RAD;
     constexpr int TASKS = LPW * B;
     constexpr int TPT = (TASKS + 63) / 64;
@@ -292,11 +285,7 @@ __device__ __forceinline__ void wave_stage(C2<R> *__restrict__ buf, int LS, int 
             const int k = j % P;
             C2<R> *b = buf + line * LS;
 #pragma unroll
-            for (int q = 0; q < RAD; ++q) {
-                const int e = (j - k) * RAD + k + q * P;
-                epi(line, e, v[t][q]);  // output e of local line `line` (final stage: frequency e)
-                b[padded<MW, G>(e) * ES] = v[t][q];
-            }
+            for (int q = 0; q < RAD; ++q) b[padded<MW, G>((j - k) * RAD + k + q * P) * ES] = v[t][q];
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -313,30 +302,19 @@ struct WaveFft {
     static constexpr bool TWO = num_stages(L) == 2;
     static constexpr int MODE = !TWO ? 0 : (LINE_FAST ? 2 : 1);   // intermediate layout
     static constexpr int SPAN = MODE == 1 ? L + L / R1 : L;       // slots a line needs
-    template <int P, class Epi>
-    static __device__ __forceinline__ void from(C2<R> *buf, int LS, int ES, const C2<R> *tw, int lane, Epi &epi) {
+    template <int P>
+    static __device__ __forceinline__ void from(C2<R> *buf, int LS, int ES, const C2<R> *tw, int lane) {
         if constexpr (P < L) {
             constexpr int RAD = stage_radix(L / P);
             static_assert(RAD > 1, "length must factor into 2, 3");
             constexpr int MR = (TWO && P > 1) ? MODE : 0;
             constexpr int MW = (TWO && P == 1) ? MODE : 0;
-            if constexpr (P * RAD == L)
-                wave_stage<R, L, P, RAD, LPW, SIGN, LINE_FAST, TWS, MR, MW, R1>(buf, LS, ES, tw, lane, epi);
-            else
-                wave_stage<R, L, P, RAD, LPW, SIGN, LINE_FAST, TWS, MR, MW, R1>(buf, LS, ES, tw, lane);
-            from<P * RAD>(buf, LS, ES, tw, lane, epi);
+            wave_stage<R, L, P, RAD, LPW, SIGN, LINE_FAST, TWS, MR, MW, R1>(buf, LS, ES, tw, lane);
+            from<P * RAD>(buf, LS, ES, tw, lane);
         }
     }
     static __device__ __forceinline__ void run(C2<R> *buf, int LS, int ES, const C2<R> *tw, int lane) {
-        NoEpi none;
-        from<1>(buf, LS, ES, tw, lane, none);
-    }
-    // Same, with epi(line, k, value) applied to every output of the final stage
-    // (value k of local line `line`, natural order) before it is stored.
-    template <class Epi>
-    static __device__ __forceinline__ void run_epi(C2<R> *buf, int LS, int ES, const C2<R> *tw, int lane,
-                                                   Epi &epi) {
-        from<1>(buf, LS, ES, tw, lane, epi);
+        from<1>(buf, LS, ES, tw, lane);
     }
 };
 

@@ -142,13 +142,17 @@ struct Geo {
     static constexpr int LINES = S * W;              // x lines per column workgroup
     static_assert(LINES % NWC == 0, "lines split evenly over waves");
     static constexpr int LPWC = LINES / NWC;
-    // Row stride (x) of the column layout, = 4 (mod 32) complex FP32 values or
-    // = 4 (mod 16) FP64 ones: rows then start 8 (16) banks apart, which spreads both
-    // the butterfly accesses (a few lines x 16 rows) and the row-wise load/store
-    // accesses over all banks.
-    static constexpr int CSMOD = sizeof(R) == 4 ? 32 : 16;
-    static constexpr int CS = LINES + ((4 - LINES % CSMOD) + CSMOD) % CSMOD;
+    // Row stride (x) of the column layout: the smallest CS >= LINES with
+    // CS = 4 (mod 8).  Consecutive rows then start 8 x odd banks apart (FP32; 16 x odd
+    // for FP64), so 8 (4) successive rows fall on distinct groups of banks, which
+    // spreads both the butterfly accesses (a few lines x 16 rows) and the row-wise
+    // load/store accesses over all banks.
+    static constexpr int CS = LINES + ((4 - LINES % 8) + 8) % 8;
     static constexpr int NTC = 64 * NWC;
+    // column workgroups that fit one CU's LDS (at most 4) and the waves per SIMD they need
+    static constexpr int LDS_COLS = N * CS * (int)sizeof(C2<R>) + N * (int)sizeof(C2<R>) + N * 8 + 64 * NQC;
+    static constexpr int WGC_CU = (163840 / LDS_COLS) >= 4 ? 4 : (163840 / LDS_COLS) < 1 ? 1 : (163840 / LDS_COLS);
+    static constexpr int WPEC = (WGC_CU * NWC + 3) / 4 > 1 ? (WGC_CU * NWC + 3) / 4 : 1;
     static constexpr int NB_PLANE = N * S;           // plane workgroups per state
     static constexpr int NB_COLS = M * NCH;          // column workgroups per state
 };
@@ -171,6 +175,12 @@ __device__ __forceinline__ int mirror_idx(int idx, int n, int center) {
 __device__ __forceinline__ double kin_symbol(int kin, int sub, double mass, double s) {
     if (kin == ITSE_KIN_NR_CONT || kin == ITSE_KIN_NR_LAT) return s;
     const double e = sqrt(s + mass * mass);
+    return sub ? s / (e + mass) : e;
+}
+
+__device__ __forceinline__ float kin_symbol_f32(int kin, int sub, float mass, float s) {
+    if (kin == ITSE_KIN_NR_CONT || kin == ITSE_KIN_NR_LAT) return s;
+    const float e = sqrtf(s + mass * mass);
     return sub ? s / (e + mass) : e;
 }
 
@@ -421,7 +431,8 @@ k_plane_fwd(const JobRef *__restrict__ jobs) {
 // [kx][ky][kz] at `out` (for the spectrum query).
 // ---------------------------------------------------------------------------
 template <typename R, int N, int V>
-__global__ void __launch_bounds__((Geo<R, N, V>::NTC)) k_columns(const JobRef *__restrict__ jobs, int mode,
+__global__ void __launch_bounds__((Geo<R, N, V>::NTC)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPEC)))
+k_columns(const JobRef *__restrict__ jobs, int mode,
                                                               int moments, C2<R> *__restrict__ out) {
     using G = Geo<R, N, V>;
     constexpr int S = G::S, M = G::M, H = G::H, W = G::W, CS = G::CS, LPW = G::LPWC, NTC = G::NTC;
@@ -482,18 +493,45 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTC)) k_columns(const JobRef *_
         }
         return;
     }
-    // forward transform along x with the kinetic multiply T(kx, ky, kz) / N^3 (FP64
-    // symbol and product) applied to its final outputs
+    // forward transform along x, then the kinetic multiply T(kx, ky, kz) / N^3 on this
+    // wave's lines (with the momentum-space parity sums when moments are on)
+    WaveFft<R, N, LPW, -1, true, 1>::run(buf + l0, 1, CS, tw, lane);
     const double inv_n3 = 1.0 / ((double)N * (double)N * (double)N);
     const bool mom = moments && L.moments;
     const int kin = L.kin, rest = L.sub, center = L.center;
     const double mass = L.mass;
     double acc[NQC] = {0.0, 0.0};
-    auto kinetic = [&](int line, int kx, C2<R> &val) {
-        const int l = l0 + line, q = l / W, kz = kz0 + l % W;
-        if (kz >= H) return;
-        const int ky = kyp + M * q;
-        if (mom) {
+    auto multiply = [&](int kx, int ky, int kz, C2<R> &val) {
+        const double ssum = ktab[kx] + ktab[ky] + ktab[kz];
+        if constexpr (sizeof(R) == 4) {
+            // FP32 lattices: the symbol from the FP64 table sum, evaluated with
+            // correctly rounded FP32 operations (a few ulps, the transforms' own
+            // rounding level)
+            const float t = kin_symbol_f32(kin, rest, (float)mass, (float)ssum) * (float)inv_n3;
+            val.x = val.x * t;
+            val.y = val.y * t;
+        } else {
+            const double t = kin_symbol(kin, rest, mass, ssum) * inv_n3;
+            val.x = (R)((double)val.x * t);
+            val.y = (R)((double)val.y * t);
+        }
+    };
+    if (!mom) {
+#pragma unroll 1
+        for (int e = lane; e < N * LPW; e += 64) {
+            const int kx = e / LPW, l = l0 + e % LPW, q = l / W, kz = kz0 + l % W;
+            if (kz >= H) continue;
+            C2<R> val = buf[kx * CS + l];
+            multiply(kx, kyp + M * q, kz, val);
+            buf[kx * CS + l] = val;
+        }
+    } else {
+#pragma unroll 1
+        for (int e = lane; e < N * LPW; e += 64) {
+            const int kx = e / LPW, l = l0 + e % LPW, q = l / W, kz = kz0 + l % W;
+            if (kz >= H) continue;
+            const int ky = kyp + M * q;
+            C2<R> val = buf[kx * CS + l];
             // weight 2 for the interior of the half spectrum (its mirror is implied)
             const double wt = (kz == 0 || 2 * kz == N) ? 1.0 : 2.0;
             const double re = (double)val.x, im = (double)val.y;
@@ -509,12 +547,10 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTC)) k_columns(const JobRef *_
                 pr = cs * pr - sn * pim;
             }
             acc[CQ_PAR] += wt * pr;
+            multiply(kx, ky, kz, val);
+            buf[kx * CS + l] = val;
         }
-        const double t = kin_symbol(kin, rest, mass, ktab[kx] + ktab[ky] + ktab[kz]) * inv_n3;
-        val.x = (R)((double)val.x * t);
-        val.y = (R)((double)val.y * t);
-    };
-    WaveFft<R, N, LPW, -1, true, 1>::run_epi(buf + l0, 1, CS, tw, lane, kinetic);
+    }
     __builtin_amdgcn_wave_barrier();
     WaveFft<R, N, LPW, +1, true, 1>::run(buf + l0, 1, CS, tw, lane);
     if (mom) block_sums<NQC, NTC>(acc, L.part_cols + ((size_t)i * L.nb_cols + blk) * NQC, red);
