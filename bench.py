@@ -177,6 +177,77 @@ def serving_run(torch, itse, count: int, qps: float, budget: int, seed: int = 1)
             "steps_mean": float(np.mean([done[i][1]["steps"] for i in done]))}
 
 
+def _solve(itse, p, v, states, precision, tol, relative, max_steps, parity):
+    """Run one solve to |dE| <= tol per 100 steps; returns (energies, steps, seconds, lattice)."""
+    from paper_2006_16935_amd.solver import run_to_convergence
+    lat = itse.Lattice(p.n, p.a, p.mass, p.dtau, kin=p.kin, subtract_rest_mass=p.subtract_rest_mass,
+                       precision=precision, center=p.center, nstates=len(states))
+    lat.set_potential(v)
+    for i, st in enumerate(states):
+        lat.set_state(i, st)
+    lat.set_options(ortho_every=1, parity=list(parity) if parity else None)
+    res = run_to_convergence(lat, tol, relative=relative, check_every=100, max_steps=max_steps)
+    return res, lat
+
+
+def study(torch, itse, which: str, max_steps: int):
+    """Converged eigenpairs against the oracle.
+
+    precision: the 256^3 precision-form solve (3 states, parity +,-,-) in FP32 (with
+    FP64 sums) and in FP64 on the GPU, from the same FP32-rounded inputs; the oracle
+    certifies each GPU state (residual of its step map) and evaluates its energy in
+    FP64; errors are reported per eigenvalue for the FP32 energies, the FP64
+    re-evaluation of the FP32 states (polish) and the FP64 energies.
+    relativistic: the 128^3 FP64 relativistic Cornell solve with three states to
+    |dE| < 1e-10 (the first excited level is a degenerate triplet of the cubic
+    lattice, so E1 = E2); the oracle certifies the states."""
+    import oracle
+    import synth
+    out = {"study": which}
+    if which == "precision":
+        p = synth.config_precision(256)
+        v32 = p.potential_array(np.float64).astype(np.float32)
+        s32 = [s.astype(np.float32) for s in p.initial_states()]
+        r32, lat32 = _solve(itse, p, v32, s32, "fp32", p.tol, True, max_steps, p.parity)
+        polish = [lat32.polish(i)["energy"] for i in range(p.nstates)]
+        st32 = [lat32.get_state(i) for i in range(p.nstates)]
+        lat32.close()
+        r64, lat64 = _solve(itse, p, v32.astype(np.float64), [s.astype(np.float64) for s in s32], "fp64",
+                            1e-11, True, max_steps, p.parity)
+        st64 = [lat64.get_state(i) for i in range(p.nstates)]
+        lat64.close()
+        L = oracle.lattice(p.n, p.a, p.mass, p.dtau, p.kin, p.subtract_rest_mass, p.center)
+        c64 = [oracle.certify(L, st, v32.astype(np.float64)) for st in st64]
+        c32 = [oracle.certify(L, st, v32.astype(np.float64)) for st in st32]
+        ref = [c["energy"] for c in c64]
+        out.update({
+            "n": 256, "steps_fp32": r32.steps, "converged_fp32": r32.converged, "seconds_fp32": r32.wall_s,
+            "steps_fp64": r64.steps, "converged_fp64": r64.converged, "seconds_fp64": r64.wall_s,
+            "E_fp32": r32.energies, "E_polish": polish, "E_fp64": r64.energies, "E_oracle": ref,
+            "resid_fp64_states": [c["resid"] for c in c64], "resid_fp32_states": [c["resid"] for c in c32],
+            "E_oracle_of_fp32_states": [c["energy"] for c in c32],
+            "relerr_fp32": [abs(a - b) / abs(b) for a, b in zip(r32.energies, ref)],
+            "relerr_polish": [abs(a - b) / abs(b) for a, b in zip(polish, ref)],
+            "relerr_fp64": [abs(a - b) / abs(b) for a, b in zip(r64.energies, ref)],
+        })
+    else:
+        p = synth.config_relativistic_fp64(128)
+        v = p.potential_array(np.float64)
+        r, lat = _solve(itse, p, v, p.initial_states(), "fp64", 1e-10, False, max_steps, None)
+        st = [lat.get_state(i) for i in range(p.nstates)]
+        lat.evaluate(moments=True)
+        par = [lat.observe(i)["parity_even"] for i in range(p.nstates)]
+        lat.close()
+        L = oracle.lattice(p.n, p.a, p.mass, p.dtau, p.kin, p.subtract_rest_mass, p.center)
+        cert = [oracle.certify(L, s_, v) for s_ in st]
+        out.update({"n": 128, "steps": r.steps, "converged": r.converged, "seconds": r.wall_s,
+                    "site_steps_per_s": p.n ** 3 * p.nstates * r.steps / r.wall_s,
+                    "E": r.energies, "E_oracle": [c["energy"] for c in cert],
+                    "resid": [c["resid"] for c in cert], "parity_even_weight": par,
+                    "E1_minus_E2": r.energies[1] - r.energies[2]})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +260,9 @@ def main():
     ap.add_argument("--schedule", type=int, default=-1,
                     help="schedule variant for the 256^3 FP32 lattice (default: autotune)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-lattice batched leg")
+    ap.add_argument("--study", choices=["precision", "relativistic"], default=None,
+                    help="only run a converged-solve study against the oracle and print its JSON line")
+    ap.add_argument("--max-steps", type=int, default=60000)
     ap.add_argument("--serving", action="store_true",
                     help="only run the serving form (Poisson arrivals) and print its JSON line")
     ap.add_argument("--requests", type=int, default=24)
@@ -216,6 +290,9 @@ def main():
     import paper_2006_16935_amd as itse
 
     torch.cuda.set_device(0)
+    if args.study:
+        print(json.dumps(study(torch, itse, args.study, args.max_steps)), flush=True)
+        return
     if args.serving:
         res = serving_run(torch, itse, args.requests, args.qps, int(args.budget_gb * (1 << 30)))
         print(json.dumps({"metric": "p50/p99 solve latency, serving form", **res}), flush=True)
