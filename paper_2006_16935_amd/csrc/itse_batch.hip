@@ -36,6 +36,7 @@ struct itse_batch {
     hipStream_t cap = nullptr;
     std::vector<hipStream_t> branch;
     std::vector<Group> groups;
+    std::vector<std::vector<itse_lattice *>> members;  // lattices of each group
     std::vector<void *> dev_arrays;
     hipGraphExec_t graph1 = nullptr, graphN = nullptr;
     std::vector<hipEvent_t> evs;
@@ -142,6 +143,7 @@ extern "C" itse_status itse_batch_create(int count, itse_lattice *const *lats, v
         g.nlats = (int)lrefs.size();
         for (auto *L : members) g.kmax = std::max(g.kmax, L->d.nstates);
         B->groups.push_back(g);
+        B->members.push_back(members);
     }
     if (hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(ITSE_EDEVICE, "stream create"));
@@ -168,6 +170,21 @@ extern "C" itse_status itse_batch_step(itse_batch *B, int nsteps) {
         HIPCHK(hipEventRecord(ev, L->stream));
         HIPCHK(hipStreamWaitEvent(B->stream, ev, 0));
         HIPCHK(hipEventDestroy(ev));
+    }
+    // passes each group launches, from the members' current options; a change
+    // since the graphs were captured captures them again
+    bool changed = false;
+    for (size_t gi = 0; gi < B->groups.size(); ++gi) {
+        int needs = 0;
+        for (auto *L : B->members[gi]) needs |= step_needs(L->host, L->d.nstates);
+        if (needs != B->groups[gi].needs) changed = true;
+        B->groups[gi].needs = needs;
+    }
+    if (changed && (B->graph1 || B->graphN)) {
+        HIPCHK(hipStreamSynchronize(B->stream));
+        if (B->graph1) HIPCHK(hipGraphExecDestroy(B->graph1));
+        if (B->graphN) HIPCHK(hipGraphExecDestroy(B->graphN));
+        B->graph1 = B->graphN = nullptr;
     }
     const int chunk = ITSE_GRAPH_CHUNK;
     if (nsteps >= chunk && !B->graphN) {

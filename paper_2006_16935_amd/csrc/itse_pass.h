@@ -184,6 +184,51 @@ __device__ __forceinline__ float kin_symbol_f32(int kin, int sub, float mass, fl
     return sub ? s / (e + mass) : e;
 }
 
+// Kinetic symbol forms: the table sum itself (non-relativistic kinds),
+// sqrt(p^2 + m^2), and sqrt(p^2 + m^2) - m written as p^2 / (sqrt(p^2 + m^2) + m).
+enum SymKind { SYM_SUM = 0, SYM_REL = 1, SYM_REL_SUB = 2 };
+
+// T / N^3 for the table sum s.  FP64 lattices: correctly rounded FP64 operations.
+// FP32 lattices: the FP32 value of s with the hardware reciprocal square root and
+// reciprocal (a few ulps of FP32, the level of the transforms' own rounding).
+template <typename R, int KIND>
+__device__ __forceinline__ R symbol_scaled(double s, double mass, double inv_n3) {
+    if constexpr (sizeof(R) == 4) {
+        const float sf = (float)s, m = (float)mass;
+        float t = sf;
+        if constexpr (KIND != SYM_SUM) {
+            const float x = sf + m * m;
+            const float e = x * __builtin_amdgcn_rsqf(x);
+            t = KIND == SYM_REL ? e : sf * __builtin_amdgcn_rcpf(e + m);
+        }
+        return t * (float)inv_n3;
+    } else {
+        double t = s;
+        if constexpr (KIND != SYM_SUM) {
+            const double e = sqrt(s + mass * mass);
+            t = KIND == SYM_REL ? e : s / (e + mass);
+        }
+        return t * inv_n3;
+    }
+}
+
+// Multiply one x line of the column layout (stride CS) by T(kx, ky, kz) / N^3 at
+// kx = kx0, kx0 + KSTEP, ...; `cl` is the line's table sum over ky and kz.
+template <typename R, int KIND, int N, int KSTEP, int CS>
+__device__ __forceinline__ void multiply_line(C2<R> *line, const double *ktab, int kx0, double cl, double mass,
+                                              double inv_n3) {
+    constexpr int NE = N / KSTEP;
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+        const int kx = kx0 + KSTEP * k;
+        const R t = symbol_scaled<R, KIND>(ktab[kx] + cl, mass, inv_n3);
+        C2<R> v = line[kx * CS];
+        v.x *= t;
+        v.y *= t;
+        line[kx * CS] = v;
+    }
+}
+
 // Wave-level fixed-order sum of a double over the 64 lanes (lane 0 gets it).
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -517,13 +562,30 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
         }
     };
     if (!mom) {
+        if constexpr (64 % LPW == 0 && N % (64 / LPW) == 0) {
+            // each lane keeps one line (fixed ky, kz) and steps through kx
+            const int kind = kin == ITSE_KIN_NR_CONT || kin == ITSE_KIN_NR_LAT ? SYM_SUM
+                             : rest                                            ? SYM_REL_SUB
+                                                                               : SYM_REL;
+            const int l = l0 + lane % LPW, kz = kz0 + l % W;
+            const double cl = ktab[kyp + M * (l / W)] + ktab[kz < H ? kz : 0];
+            if (kz < H) {
+                if (kind == SYM_SUM)
+                    multiply_line<R, SYM_SUM, N, 64 / LPW, CS>(buf + l, ktab, lane / LPW, cl, mass, inv_n3);
+                else if (kind == SYM_REL)
+                    multiply_line<R, SYM_REL, N, 64 / LPW, CS>(buf + l, ktab, lane / LPW, cl, mass, inv_n3);
+                else
+                    multiply_line<R, SYM_REL_SUB, N, 64 / LPW, CS>(buf + l, ktab, lane / LPW, cl, mass, inv_n3);
+            }
+        } else {
 #pragma unroll 1
-        for (int e = lane; e < N * LPW; e += 64) {
-            const int kx = e / LPW, l = l0 + e % LPW, q = l / W, kz = kz0 + l % W;
-            if (kz >= H) continue;
-            C2<R> val = buf[kx * CS + l];
-            multiply(kx, kyp + M * q, kz, val);
-            buf[kx * CS + l] = val;
+            for (int e = lane; e < N * LPW; e += 64) {
+                const int kx = e / LPW, l = l0 + e % LPW, q = l / W, kz = kz0 + l % W;
+                if (kz >= H) continue;
+                C2<R> val = buf[kx * CS + l];
+                multiply(kx, kyp + M * q, kz, val);
+                buf[kx * CS + l] = val;
+            }
         }
     } else {
 #pragma unroll 1

@@ -11,6 +11,12 @@
 
 namespace itse {
 
+// Optional passes of a step: the one-state-at-a-time projection (states projected
+// along different axes) and the fused projection + Gram pass (any projection, or
+// Gram-Schmidt of more than one state).  A step without them only launches the
+// transform passes and the finalisation.
+enum StepNeeds { NEED_PROJECT = 1, NEED_GRAM = 2 };
+
 // A set of jobs of equal (n, precision, schedule) stepped by the same launches.
 struct Group {
     int n = 0, prec = 0, variant = 0;
@@ -19,9 +25,11 @@ struct Group {
     const JobRef *lats = nullptr;  // device array of (lattice, 0)
     int nlats = 0;
     int kmax = 1;                  // largest number of states among the lattices
+    int needs = NEED_PROJECT | NEED_GRAM;  // optional passes a step launches
 };
 
 itse_status fail(itse_status st, const char *fmt, ...);
+int step_needs(const LatDev &opts, int nstates);
 hipError_t enqueue_step(const Group &g, hipStream_t s);
 hipError_t enqueue_eval(const Group &g, hipStream_t s);
 itse_status capture_steps(hipStream_t cap, const std::vector<Group> &groups, int nsteps,
@@ -57,6 +65,7 @@ struct itse_lattice {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph1 = nullptr;
     hipGraphExec_t graphN = nullptr;
+    int graph_needs = -1;              // optional passes captured in graph1 / graphN
     itse_lattice *shadow = nullptr;    // FP64 twin for polish
     void *cur_raw(int i) const { return itse::state_buf(host, steps_host, 0, i); }
     void *stage_buf(size_t bytes);

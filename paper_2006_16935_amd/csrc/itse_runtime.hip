@@ -51,7 +51,7 @@ extern "C" const char *itse_last_error(void) { return g_err.c_str(); }
 extern "C" const char *itse_version(void) { return "itse 0.1 (gfx950)"; }
 
 // ------------------------------------------------------------------------------------
-// Finalisation kernel: one workgroup per lattice.
+// Finalisation kernels: the step's sums, then observables and coefficients.
 // ------------------------------------------------------------------------------------
 namespace itse {
 
@@ -59,169 +59,170 @@ constexpr int FIN_NT = 512;
 // Largest number of sums one lattice needs: rows and columns of every state, Gram.
 constexpr int FIN_QMAX = MAXK * (NQR + NQC) + MAXK * (MAXK + 1) / 2;
 
-// Finalisation: workgroup (q, lattice) forms sum number q of the lattice from the
-// per-workgroup partials in a fixed order and stores it in the lattice record;
-// the last workgroup of the lattice to finish (counted with an atomic counter,
-// which it resets) forms the observables, the Gram-Schmidt coefficients and the
-// normalisation.  Results do not depend on which workgroup finishes last.
-__global__ void __launch_bounds__(FIN_NT) k_finalize(const JobRef *__restrict__ lats, int mode) {
+// Which sums a finalisation forms: K * NQR row sums, K * NQC column sums (when
+// moments are on) and, when Gram sums exist, the K (K + 1) / 2 Gram entries.  Gram
+// sums of the updated (and projected) arrays exist on orthogonalisation steps and
+// whenever states are projected (their diagonal then gives the norms).
+struct FinLayout {
+    bool ortho_step, have_gram;
+    int q_rows, q_cols, q_gram, total;
+};
+
+__device__ __forceinline__ FinLayout fin_layout(const LatDev &L, int mode) {
+    FinLayout f;
+    const int K = L.nstates;
+    f.ortho_step = (mode == FIN_STEP) && K > 1 && L.ortho_every > 0 && ((L.step + 1) % L.ortho_every) == 0;
+    f.have_gram = (mode == FIN_STEP) && (f.ortho_step || L.proj_mode != 0);
+    f.q_rows = K * NQR;
+    f.q_cols = L.moments ? K * NQC : 0;
+    f.q_gram = f.have_gram ? K * (K + 1) / 2 : 0;
+    f.total = f.q_rows + f.q_cols + f.q_gram;
+    return f;
+}
+
+// Finalisation, first kernel: workgroup (q, lattice) forms sum number q of the
+// lattice from the per-workgroup partials of the step's passes, in a fixed order,
+// and stores it in the lattice record.
+__global__ void __launch_bounds__(FIN_NT) k_fin_sums(const JobRef *__restrict__ lats, int mode) {
     constexpr int NG = MAXK * (MAXK + 1) / 2;
     __shared__ double red[FIN_NT / 64];
-    __shared__ int last;
     LatDev &L = *lats[blockIdx.y].lat;
-    const int K = L.nstates;
-    const bool ortho_step = (mode == FIN_STEP) && K > 1 && L.ortho_every > 0 &&
-                            ((L.step + 1) % L.ortho_every) == 0;
-    // Gram sums of the updated (and projected) arrays exist on orthogonalisation steps
-    // and whenever states are projected (their diagonal then gives the norms)
-    const bool have_gram = (mode == FIN_STEP) && (ortho_step || L.proj_mode != 0);
-    // sums: K*NQR row sums, K*NQC column sums (moments), Gram entries
-    const int q_rows = K * NQR;
-    const int q_cols = L.moments ? K * NQC : 0;
-    const int q_gram = have_gram ? K * (K + 1) / 2 : 0;
-    const int total = q_rows + q_cols + q_gram;
+    const FinLayout f = fin_layout(L, mode);
     const int q = blockIdx.x;
-    if (q >= total) return;
-    {
-        const double *p;
-        int count, stride;
-        if (q < q_rows) {
-            const int i = q / NQR, c = q % NQR;
-            p = L.part_rows + (size_t)i * L.nb_rows * NQR + c;
-            count = L.nb_rows;
-            stride = NQR;
-        } else if (q < q_rows + q_cols) {
-            const int t = q - q_rows, i = t / NQC, c = t % NQC;
-            p = L.part_cols + (size_t)i * L.nb_cols * NQC + c;
-            count = L.nb_cols;
-            stride = NQC;
-        } else {
-            const int slot = q - q_rows - q_cols;  // l (l + 1) / 2 + j
-            p = L.part_gram + slot;
-            count = L.nb_gram;
-            stride = NG;
-        }
-        // up to 8 loads in flight per thread, added in a fixed order
-        double acc[1] = {0.0};
-        for (int b0 = 0; b0 < count; b0 += 8 * FIN_NT) {
-            double v[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int b = b0 + t * FIN_NT + threadIdx.x;
-                v[t] = b < count ? p[(size_t)b * stride] : 0.0;
-            }
-#pragma unroll
-            for (int t = 0; t < 8; ++t) acc[0] += v[t];
-        }
-        block_sums<1, FIN_NT>(acc, &L.fin_sums[q], red);
+    if (q >= f.total) return;
+    const double *p;
+    int count, stride;
+    if (q < f.q_rows) {
+        const int i = q / NQR, c = q % NQR;
+        p = L.part_rows + (size_t)i * L.nb_rows * NQR + c;
+        count = L.nb_rows;
+        stride = NQR;
+    } else if (q < f.q_rows + f.q_cols) {
+        const int t = q - f.q_rows, i = t / NQC, c = t % NQC;
+        p = L.part_cols + (size_t)i * L.nb_cols * NQC + c;
+        count = L.nb_cols;
+        stride = NQC;
+    } else {
+        const int slot = q - f.q_rows - f.q_cols;  // l (l + 1) / 2 + j
+        p = L.part_gram + slot;
+        count = L.nb_gram;
+        stride = NG;
     }
-    // the last workgroup of this lattice continues
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const int done = atomicAdd(&L.fin_count, 1);
-        last = (done == total - 1);
+    // up to 8 loads in flight per thread, added in a fixed order
+    double acc[1] = {0.0};
+    for (int b0 = 0; b0 < count; b0 += 8 * FIN_NT) {
+        double v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int b = b0 + t * FIN_NT + threadIdx.x;
+            v[t] = b < count ? p[(size_t)b * stride] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[0] += v[t];
     }
-    __syncthreads();
-    if (!last) return;
-    // all sums of the lattice, read past the (non-coherent) L1 by one thread each
+    block_sums<1, FIN_NT>(acc, &L.fin_sums[q], red);
+}
+
+// Finalisation, second kernel (one wave per lattice): the observables of the
+// states at the start of the step (lane i: state i), and on step finalisation
+// the coefficients of the new states in terms of the raw updated arrays:
+// Gram-Schmidt in state order as G = R^T R (Cholesky, R upper triangular), new
+// states U R^{-1}, or the normalisation alone.  A non-finite or non-positive sum
+// sets the lattice's error flags and keeps the previous coefficients.
+__global__ void __launch_bounds__(64) k_fin_tail(const JobRef *__restrict__ lats, int mode) {
+    LatDev &L = *lats[blockIdx.x].lat;
+    const FinLayout f = fin_layout(L, mode);
+    const int K = L.nstates;
+    const int lane = threadIdx.x;
     __shared__ double sums[FIN_QMAX];
-    if (threadIdx.x < total)
-        sums[threadIdx.x] = __hip_atomic_load(&L.fin_sums[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    L.fin_count = 0;
-    // the serial tail works in LDS (per-thread arrays indexed by the runtime state
-    // count would live in scratch memory)
-    __shared__ double rows[MAXK][NQR];
-    __shared__ double cols[MAXK][NQC];
-    __shared__ double gram[NG];
     __shared__ double M[MAXK][MAXK];
     __shared__ double Rm[MAXK][MAXK];
-    for (int i = 0; i < K; ++i)
-        for (int c = 0; c < NQR; ++c) rows[i][c] = sums[i * NQR + c];
-    for (int i = 0; i < K; ++i)
-        for (int c = 0; c < NQC; ++c) cols[i][c] = q_cols ? sums[q_rows + i * NQC + c] : 0.0;
-    for (int g = 0; g < q_gram; ++g) gram[g] = sums[q_rows + q_cols + g];
+    __shared__ int errs[64];
+    for (int t = lane; t < f.total; t += 64) sums[t] = L.fin_sums[t];
+    __syncthreads();
     int err = 0;
-    // observables of the states at the start of the step
-    for (int i = 0; i < K; ++i) {
+    if (lane < K) {
+        const double *rows = sums + lane * NQR;
+        const double *cols = sums + f.q_rows + lane * NQC;
         ObsDev o;
-        const double pp = rows[i][RQ_PP];
+        const double pp = rows[RQ_PP];
         o.step = L.step;
         o.norm2 = pp;
-        o.kinetic = rows[i][RQ_PK] / pp;
-        o.potential = rows[i][RQ_VPP] / pp;
-        o.energy = (rows[i][RQ_PK] + rows[i][RQ_VPP]) / pp;
+        o.kinetic = rows[RQ_PK] / pp;
+        o.potential = rows[RQ_VPP] / pp;
+        o.energy = (rows[RQ_PK] + rows[RQ_VPP]) / pp;
         if (L.moments) {
-            o.x = rows[i][RQ_X] / pp;
-            o.y = rows[i][RQ_Y] / pp;
-            o.z = rows[i][RQ_Z] / pp;
-            o.r2 = rows[i][RQ_R2] / pp;
-            o.parity_even = 0.5 * (1.0 + cols[i][CQ_PAR] / cols[i][CQ_NORM]);
+            o.x = rows[RQ_X] / pp;
+            o.y = rows[RQ_Y] / pp;
+            o.z = rows[RQ_Z] / pp;
+            o.r2 = rows[RQ_R2] / pp;
+            o.parity_even = 0.5 * (1.0 + cols[CQ_PAR] / cols[CQ_NORM]);
         } else {
             o.x = o.y = o.z = o.r2 = 0.0;
             o.parity_even = -1.0;
         }
         if (!isfinite(o.energy) || !isfinite(pp) || pp <= 0.0) err |= 1;
-        L.obs[i] = o;
-        if (mode == FIN_STEP && L.hist) L.hist[(size_t)(L.step % HIST_CAP) * MAXK + i] = o;
+        L.obs[lane] = o;
+        if (mode == FIN_STEP && L.hist) L.hist[(size_t)(L.step % HIST_CAP) * MAXK + lane] = o;
     }
-    if (mode != FIN_STEP) {
-        if (err) L.error |= err;
-        return;
-    }
-    // coefficients of the new states in terms of the raw updated arrays
-    for (int j = 0; j < MAXK; ++j)
-        for (int i = 0; i < MAXK; ++i) M[j][i] = 0.0;
-    bool done = false;
-    if (ortho_step) {
-        // G = R^T R (R upper); new states = U R^{-1}
-        bool ok = true;
-        for (int j = 0; j < K && ok; ++j) {
-            for (int i = j; i < K; ++i) {
-                double s = gram[i * (i + 1) / 2 + j];
-                for (int l = 0; l < j; ++l) s -= Rm[l][j] * Rm[l][i];
-                if (i == j) {
-                    if (!(s > 0.0) || !isfinite(s)) {
-                        ok = false;
-                        break;
-                    }
-                    Rm[j][j] = sqrt(s);
-                } else {
-                    Rm[j][i] = s / Rm[j][j];
-                }
-            }
-        }
-        if (ok) {
-            for (int i = 0; i < K; ++i) {
-                M[i][i] = 1.0 / Rm[i][i];
-                for (int j = i - 1; j >= 0; --j) {
-                    double s = 0.0;
-                    for (int l = j + 1; l <= i; ++l) s += Rm[j][l] * M[l][i];
-                    M[j][i] = -s / Rm[j][j];
-                }
-            }
-            done = true;
-        } else {
-            err |= 2;
-        }
-    }
-    if (!done) {
-        for (int i = 0; i < K; ++i) {
-            const double nn = have_gram ? gram[i * (i + 1) / 2 + i] : rows[i][RQ_UU];
-            if (!(nn > 0.0) || !isfinite(nn)) err |= 1;
-            M[i][i] = 1.0 / sqrt(nn);
-        }
-    }
-    for (int j = 0; j < MAXK; ++j)
-        for (int i = 0; i < MAXK; ++i)
-            if (!isfinite(M[j][i])) err |= 1;
-    if (!err) {
+    if (mode == FIN_STEP && lane == 0) {
+        const double *gram = sums + f.q_rows + f.q_cols;
         for (int j = 0; j < MAXK; ++j)
-            for (int i = 0; i < MAXK; ++i) L.coef[j][i] = M[j][i];
+            for (int i = 0; i < MAXK; ++i) M[j][i] = 0.0;
+        bool done = false;
+        if (f.ortho_step) {
+            bool ok = true;
+            for (int j = 0; j < K && ok; ++j) {
+                for (int i = j; i < K; ++i) {
+                    double s = gram[i * (i + 1) / 2 + j];
+                    for (int l = 0; l < j; ++l) s -= Rm[l][j] * Rm[l][i];
+                    if (i == j) {
+                        if (!(s > 0.0) || !isfinite(s)) {
+                            ok = false;
+                            break;
+                        }
+                        Rm[j][j] = sqrt(s);
+                    } else {
+                        Rm[j][i] = s / Rm[j][j];
+                    }
+                }
+            }
+            if (ok) {
+                for (int i = 0; i < K; ++i) {
+                    M[i][i] = 1.0 / Rm[i][i];
+                    for (int j = i - 1; j >= 0; --j) {
+                        double s = 0.0;
+                        for (int l = j + 1; l <= i; ++l) s += Rm[j][l] * M[l][i];
+                        M[j][i] = -s / Rm[j][j];
+                    }
+                }
+                done = true;
+            } else {
+                err |= 2;
+            }
+        }
+        if (!done) {
+            for (int i = 0; i < K; ++i) {
+                const double nn = f.have_gram ? gram[i * (i + 1) / 2 + i] : sums[i * NQR + RQ_UU];
+                if (!(nn > 0.0) || !isfinite(nn)) err |= 1;
+                M[i][i] = 1.0 / sqrt(nn);
+            }
+        }
     }
-    L.error |= err;
-    L.step += 1;
+    __syncthreads();
+    // one coefficient per lane
+    static_assert(MAXK * MAXK == 64, "one coefficient per lane");
+    const double mv = mode == FIN_STEP ? M[lane / MAXK][lane % MAXK] : 0.0;
+    if (!isfinite(mv)) err |= 1;
+    errs[lane] = err;
+    __syncthreads();
+    int all = 0;
+    for (int t = 0; t < 64; ++t) all |= errs[t];
+    if (mode == FIN_STEP && !all) L.coef[lane / MAXK][lane % MAXK] = mv;
+    if (lane == 0) {
+        L.error |= all;
+        if (mode == FIN_STEP) L.step += 1;
+    }
 }
 
 // Device-side check of 1 + dtau min(V)/2 > 0 and finiteness (for device-provided V).
@@ -241,7 +242,10 @@ __global__ void __launch_bounds__(NT) k_check_potential(const LatDev *lp) {
 
 hipError_t launch_finalize(const JobRef *lats, int nlats, int mode, hipStream_t s) {
     if (nlats <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_finalize, dim3(FIN_QMAX, nlats), dim3(FIN_NT), 0, s, lats, mode);
+    hipLaunchKernelGGL(k_fin_sums, dim3(FIN_QMAX, nlats), dim3(FIN_NT), 0, s, lats, mode);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fin_tail, dim3(nlats), dim3(64), 0, s, lats, mode);
     return hipGetLastError();
 }
 
@@ -346,12 +350,22 @@ static hipError_t seq_forward_kin(const Group &g, int inv_mode, hipStream_t s) {
     return Launch<R>::plane_inv(g.n, g.variant, inv_mode, g.jobs, g.njobs, s);
 }
 
+int step_needs(const LatDev &o, int nstates) {
+    int m = 0;
+    if (o.proj_mode == 2) m |= NEED_PROJECT;
+    if (o.proj_mode != 0 || (nstates > 1 && o.ortho_every > 0)) m |= NEED_GRAM;
+    return m;
+}
+
 template <typename R>
 static hipError_t seq_step(const Group &g, hipStream_t s) {
     hipError_t e;
     if ((e = seq_forward_kin<R>(g, INV_UPDATE, s)) != hipSuccess) return e;
-    if ((e = Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, 1, s)) != hipSuccess) return e;
-    if ((e = Launch<R>::project_gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s)) != hipSuccess) return e;
+    if ((g.needs & NEED_PROJECT) && (e = Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, 1, s)) != hipSuccess)
+        return e;
+    if ((g.needs & NEED_GRAM) &&
+        (e = Launch<R>::project_gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s)) != hipSuccess)
+        return e;
     return launch_finalize(g.lats, g.nlats, FIN_STEP, s);
 }
 
@@ -448,6 +462,7 @@ Group single_group(itse_lattice *L) {
     g.lats = L->lat_dev;
     g.nlats = 1;
     g.kmax = L->d.nstates;
+    g.needs = step_needs(L->host, L->d.nstates);
     return g;
 }
 
@@ -840,6 +855,14 @@ extern "C" itse_status itse_step(itse_lattice *L, int nsteps, const itse_step_op
         return ITSE_OK;
     }
     if (!L->cap_stream) HIPCHK(hipStreamCreateWithFlags(&L->cap_stream, hipStreamNonBlocking));
+    if (L->graph_needs != g.needs) {
+        // the options changed which passes a step launches: capture again
+        HIPCHK(hipStreamSynchronize(L->stream));
+        if (L->graph1) HIPCHK(hipGraphExecDestroy(L->graph1));
+        if (L->graphN) HIPCHK(hipGraphExecDestroy(L->graphN));
+        L->graph1 = L->graphN = nullptr;
+        L->graph_needs = g.needs;
+    }
     std::vector<hipStream_t> br{L->cap_stream};
     const int chunk = ITSE_GRAPH_CHUNK;
     if (nsteps >= chunk && !L->graphN) {
@@ -1091,8 +1114,9 @@ static hipError_t launch_pass(const Group &g, int p, hipStream_t s) {
     case 0: return Launch<R>::plane_fwd(g.n, g.variant, g.jobs, g.njobs, s);
     case 1: return Launch<R>::columns(g.n, g.variant, COL_KIN, 1, g.jobs, g.njobs, nullptr, s);
     case 2: return Launch<R>::plane_inv(g.n, g.variant, INV_UPDATE, g.jobs, g.njobs, s);
-    case 3: return Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, 1, s);
-    case 4: return Launch<R>::project_gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s);
+    case 3: return (g.needs & NEED_PROJECT) ? Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, 1, s) : hipSuccess;
+    case 4:
+        return (g.needs & NEED_GRAM) ? Launch<R>::project_gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s) : hipSuccess;
     default: return launch_finalize(g.lats, g.nlats, FIN_STEP, s);
     }
 }
