@@ -318,4 +318,61 @@ struct WaveFft {
     }
 };
 
+// Forward transform, a pointwise map of the spectrum, and inverse transform of
+// LPW lines of a two-stage length L = G * G.  The last forward stage leaves in
+// the lane of butterfly j the outputs j + G q (q < G), which are exactly the
+// inputs of the inverse transform's first butterfly j; so the map and these two
+// stages run in registers, with no pass through LDS between them.
+// map(line, j, v) receives v[q] = X[j + G q] of local line `line`.
+template <typename R, int L, int LPW, bool LINE_FAST, int TWS>
+struct WaveFftPair {
+    static constexpr int G = stage_radix(L);
+    static constexpr bool OK = num_stages(L) == 2 && G * G == L;
+    static constexpr int MODE = LINE_FAST ? 2 : 1;
+    static constexpr int SPAN = MODE == 1 ? L + L / G : L;
+    template <typename F>
+    static __device__ __forceinline__ void run(C2<R> *buf, int LS, int ES, const C2<R> *tw, int lane, F &&map) {
+        static_assert(OK, "square two-stage lengths only");
+        constexpr int B = G;
+        constexpr int TASKS = LPW * B;
+        constexpr int TPT = (TASKS + 63) / 64;
+        wave_stage<R, L, 1, G, LPW, -1, LINE_FAST, TWS, 0, MODE, G>(buf, LS, ES, tw, lane);
+        C2<R> v[TPT][G];
+#pragma unroll
+        for (int t = 0; t < TPT; ++t) {
+            const int task = lane + 64 * t;
+            if (TASKS % 64 == 0 || task < TASKS) {
+                const int line = LINE_FAST ? task % LPW : task / B;
+                const int j = LINE_FAST ? task / LPW : task % B;
+                const C2<R> *b = buf + line * LS;
+                // second forward stage (P = G): input m twiddled by w_L^(j m)
+#pragma unroll
+                for (int m = 0; m < G; ++m) {
+                    C2<R> a = b[padded<MODE, G>(j + m * B) * ES];
+                    if (m > 0) a = cmul(a, tw[(j * m) * TWS]);
+                    v[t][m] = a;
+                }
+                Dft<G, -1, R>::run(v[t]);
+                map(line, j, v[t]);
+                // first inverse stage (P = 1): no twiddles
+                Dft<G, +1, R>::run(v[t]);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int t = 0; t < TPT; ++t) {
+            const int task = lane + 64 * t;
+            if (TASKS % 64 == 0 || task < TASKS) {
+                const int line = LINE_FAST ? task % LPW : task / B;
+                const int j = LINE_FAST ? task / LPW : task % B;
+                C2<R> *b = buf + line * LS;
+#pragma unroll
+                for (int q = 0; q < G; ++q) b[padded<MODE, G>(j * G + q) * ES] = v[t][q];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        wave_stage<R, L, G, G, LPW, +1, LINE_FAST, TWS, MODE, 0, G>(buf, LS, ES, tw, lane);
+    }
+};
+
 }  // namespace itse

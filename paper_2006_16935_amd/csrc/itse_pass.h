@@ -27,6 +27,8 @@
 // Gram-Schmidt cost no extra pass).
 #pragma once
 
+#include <type_traits>
+
 #include "itse_fft.h"
 #include "itse_internal.h"
 
@@ -539,82 +541,109 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
         return;
     }
     // forward transform along x, then the kinetic multiply T(kx, ky, kz) / N^3 on this
-    // wave's lines (with the momentum-space parity sums when moments are on)
-    WaveFft<R, N, LPW, -1, true, 1>::run(buf + l0, 1, CS, tw, lane);
+    // wave's lines (with the momentum-space parity sums when moments are on), then
+    // the inverse transform along x
     const double inv_n3 = 1.0 / ((double)N * (double)N * (double)N);
     const bool mom = moments && L.moments;
     const int kin = L.kin, rest = L.sub, center = L.center;
     const double mass = L.mass;
+    const int kind = kin == ITSE_KIN_NR_CONT || kin == ITSE_KIN_NR_LAT ? SYM_SUM : rest ? SYM_REL_SUB : SYM_REL;
     double acc[NQC] = {0.0, 0.0};
-    auto multiply = [&](int kx, int ky, int kz, C2<R> &val) {
-        const double ssum = ktab[kx] + ktab[ky] + ktab[kz];
-        if constexpr (sizeof(R) == 4) {
-            // FP32 lattices: the symbol from the FP64 table sum, evaluated with
-            // correctly rounded FP32 operations (a few ulps, the transforms' own
-            // rounding level)
-            const float t = kin_symbol_f32(kin, rest, (float)mass, (float)ssum) * (float)inv_n3;
-            val.x = val.x * t;
-            val.y = val.y * t;
-        } else {
-            const double t = kin_symbol(kin, rest, mass, ssum) * inv_n3;
-            val.x = (R)((double)val.x * t);
-            val.y = (R)((double)val.y * t);
+    using Pair = WaveFftPair<R, N, LPW, true, 1>;
+    bool fused = false;
+    if constexpr (Pair::OK) {
+        if (!mom) {
+            // square lengths: the multiply between the last forward and the first
+            // inverse stage, in registers
+            auto run = [&](auto kc) {
+                constexpr int KIND = decltype(kc)::value;
+                Pair::run(buf + l0, 1, CS, tw, lane, [&](int line, int j, C2<R>(&v)[Pair::G]) {
+                    const int l = l0 + line, kz = kz0 + l % W;
+                    if (kz >= H) return;
+                    const double cl = ktab[kyp + M * (l / W)] + ktab[kz];
+#pragma unroll
+                    for (int q = 0; q < Pair::G; ++q) {
+                        const R t = symbol_scaled<R, KIND>(ktab[j + Pair::G * q] + cl, mass, inv_n3);
+                        v[q].x *= t;
+                        v[q].y *= t;
+                    }
+                });
+            };
+            if (kind == SYM_SUM) run(std::integral_constant<int, SYM_SUM>{});
+            else if (kind == SYM_REL) run(std::integral_constant<int, SYM_REL>{});
+            else run(std::integral_constant<int, SYM_REL_SUB>{});
+            fused = true;
         }
-    };
-    if (!mom) {
-        if constexpr (64 % LPW == 0 && N % (64 / LPW) == 0) {
-            // each lane keeps one line (fixed ky, kz) and steps through kx
-            const int kind = kin == ITSE_KIN_NR_CONT || kin == ITSE_KIN_NR_LAT ? SYM_SUM
-                             : rest                                            ? SYM_REL_SUB
-                                                                               : SYM_REL;
-            const int l = l0 + lane % LPW, kz = kz0 + l % W;
-            const double cl = ktab[kyp + M * (l / W)] + ktab[kz < H ? kz : 0];
-            if (kz < H) {
-                if (kind == SYM_SUM)
-                    multiply_line<R, SYM_SUM, N, 64 / LPW, CS>(buf + l, ktab, lane / LPW, cl, mass, inv_n3);
-                else if (kind == SYM_REL)
-                    multiply_line<R, SYM_REL, N, 64 / LPW, CS>(buf + l, ktab, lane / LPW, cl, mass, inv_n3);
-                else
-                    multiply_line<R, SYM_REL_SUB, N, 64 / LPW, CS>(buf + l, ktab, lane / LPW, cl, mass, inv_n3);
+    }
+    if (!fused) {
+        WaveFft<R, N, LPW, -1, true, 1>::run(buf + l0, 1, CS, tw, lane);
+        auto multiply = [&](int kx, int ky, int kz, C2<R> &val) {
+            const double ssum = ktab[kx] + ktab[ky] + ktab[kz];
+            if constexpr (sizeof(R) == 4) {
+                // FP32 lattices: the symbol from the FP64 table sum, evaluated with
+                // correctly rounded FP32 operations (a few ulps, the transforms' own
+                // rounding level)
+                const float t = kin_symbol_f32(kin, rest, (float)mass, (float)ssum) * (float)inv_n3;
+                val.x = val.x * t;
+                val.y = val.y * t;
+            } else {
+                const double t = kin_symbol(kin, rest, mass, ssum) * inv_n3;
+                val.x = (R)((double)val.x * t);
+                val.y = (R)((double)val.y * t);
+            }
+        };
+        if (!mom) {
+            if constexpr (64 % LPW == 0 && N % (64 / LPW) == 0) {
+                // each lane keeps one line (fixed ky, kz) and steps through kx
+                const int l = l0 + lane % LPW, kz = kz0 + l % W;
+                const double cl = ktab[kyp + M * (l / W)] + ktab[kz < H ? kz : 0];
+                if (kz < H) {
+                    if (kind == SYM_SUM)
+                        multiply_line<R, SYM_SUM, N, 64 / LPW, CS>(buf + l, ktab, lane / LPW, cl, mass, inv_n3);
+                    else if (kind == SYM_REL)
+                        multiply_line<R, SYM_REL, N, 64 / LPW, CS>(buf + l, ktab, lane / LPW, cl, mass, inv_n3);
+                    else
+                        multiply_line<R, SYM_REL_SUB, N, 64 / LPW, CS>(buf + l, ktab, lane / LPW, cl, mass, inv_n3);
+                }
+            } else {
+#pragma unroll 1
+                for (int e = lane; e < N * LPW; e += 64) {
+                    const int kx = e / LPW, l = l0 + e % LPW, q = l / W, kz = kz0 + l % W;
+                    if (kz >= H) continue;
+                    C2<R> val = buf[kx * CS + l];
+                    multiply(kx, kyp + M * q, kz, val);
+                    buf[kx * CS + l] = val;
+                }
             }
         } else {
 #pragma unroll 1
             for (int e = lane; e < N * LPW; e += 64) {
                 const int kx = e / LPW, l = l0 + e % LPW, q = l / W, kz = kz0 + l % W;
                 if (kz >= H) continue;
+                const int ky = kyp + M * q;
                 C2<R> val = buf[kx * CS + l];
-                multiply(kx, kyp + M * q, kz, val);
+                // weight 2 for the interior of the half spectrum (its mirror is implied)
+                const double wt = (kz == 0 || 2 * kz == N) ? 1.0 : 2.0;
+                const double re = (double)val.x, im = (double)val.y;
+                acc[CQ_NORM] += wt * (re * re + im * im);
+                // <psi|P psi> = sum_k e^{i kappa} conj(psi_k)^2 / N^3 with kappa = 2 pi (kx+ky+kz)/N
+                // for the off-grid centre (x -> N-1-x), kappa = 0 for the origin
+                double pr = re * re - im * im;
+                const double pim = -2.0 * re * im;
+                if (center == ITSE_CENTER_CELL) {
+                    const int mm = (kx + ky + kz) % N;
+                    double sn, cs;
+                    sincospi(2.0 * (double)mm / (double)N, &sn, &cs);
+                    pr = cs * pr - sn * pim;
+                }
+                acc[CQ_PAR] += wt * pr;
+                multiply(kx, ky, kz, val);
                 buf[kx * CS + l] = val;
             }
         }
-    } else {
-#pragma unroll 1
-        for (int e = lane; e < N * LPW; e += 64) {
-            const int kx = e / LPW, l = l0 + e % LPW, q = l / W, kz = kz0 + l % W;
-            if (kz >= H) continue;
-            const int ky = kyp + M * q;
-            C2<R> val = buf[kx * CS + l];
-            // weight 2 for the interior of the half spectrum (its mirror is implied)
-            const double wt = (kz == 0 || 2 * kz == N) ? 1.0 : 2.0;
-            const double re = (double)val.x, im = (double)val.y;
-            acc[CQ_NORM] += wt * (re * re + im * im);
-            // <psi|P psi> = sum_k e^{i kappa} conj(psi_k)^2 / N^3 with kappa = 2 pi (kx+ky+kz)/N
-            // for the off-grid centre (x -> N-1-x), kappa = 0 for the origin
-            double pr = re * re - im * im;
-            const double pim = -2.0 * re * im;
-            if (center == ITSE_CENTER_CELL) {
-                const int mm = (kx + ky + kz) % N;
-                double sn, cs;
-                sincospi(2.0 * (double)mm / (double)N, &sn, &cs);
-                pr = cs * pr - sn * pim;
-            }
-            acc[CQ_PAR] += wt * pr;
-            multiply(kx, ky, kz, val);
-            buf[kx * CS + l] = val;
-        }
+        __builtin_amdgcn_wave_barrier();
+        WaveFft<R, N, LPW, +1, true, 1>::run(buf + l0, 1, CS, tw, lane);
     }
-    __builtin_amdgcn_wave_barrier();
-    WaveFft<R, N, LPW, +1, true, 1>::run(buf + l0, 1, CS, tw, lane);
     if (mom) block_sums<NQC, NTC>(acc, L.part_cols + ((size_t)i * L.nb_cols + blk) * NQC, red);
     __syncthreads();
     for (int e = tid; e < N * W; e += NTC) {
