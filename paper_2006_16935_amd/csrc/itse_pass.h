@@ -349,8 +349,39 @@ struct PairChunks {
 
 // Copy of a contiguous global block of E complex values into LDS rows of length
 // RL with stride RS, all loads of the calling thread issued first.
+// FP32 rows copied two values per thread (16-byte accesses): needs even strides
+// and, for rows of odd length, one slot of padding after each row in both layouts
+// (it receives the padding value of the other side, which nothing reads).
+template <typename R, int RL, int GS, int RS>
+constexpr bool PAIR_ROWS = sizeof(R) == 4 && GS % 2 == 0 && RS % 2 == 0 && RL + RL % 2 <= GS && RL + RL % 2 <= RS;
+
 template <typename R, int E, int RL, int GS, int RS, int NTH>
 __device__ __forceinline__ void block_load_rows(const C2<R> *src_, C2<R> *dst, int tid) {
+    if constexpr (PAIR_ROWS<R, RL, GS, RS>) {
+        using F4 = float __attribute__((ext_vector_type(4)));
+        static_assert(E % RL == 0, "whole rows");
+        constexpr int RP = (RL + 1) / 2, EP = E / RL * RP;
+        constexpr int T = (EP + NTH - 1) / NTH;
+        constexpr int TB = 8;
+        const ITSE_GLOBAL F4 *src = (const ITSE_GLOBAL F4 *)gmem(src_);
+        F4 *d4 = (F4 *)dst;
+#pragma unroll
+        for (int t0 = 0; t0 < T; t0 += TB) {
+            F4 v[TB];
+#pragma unroll
+            for (int t = 0; t < TB; ++t) {
+                const int e = tid + (t0 + t) * NTH;
+                const int ee = (EP % NTH == 0 || e < EP) ? e : EP - 1;
+                if (t0 + t < T) v[t] = src[(ee / RP) * (GS / 2) + ee % RP];
+            }
+#pragma unroll
+            for (int t = 0; t < TB; ++t) {
+                const int e = tid + (t0 + t) * NTH;
+                if (t0 + t < T && (EP % NTH == 0 || e < EP)) d4[(e / RP) * (RS / 2) + e % RP] = v[t];
+            }
+        }
+        return;
+    }
     const ITSE_GLOBAL C2<R> *src = gmem(src_);
     constexpr int T = (E + NTH - 1) / NTH;
     constexpr int TB = 32 / (int)sizeof(C2<R>) * 2;  // loads in flight per batch: 8 (FP32), 4 (FP64)
@@ -374,6 +405,20 @@ __device__ __forceinline__ void block_load_rows(const C2<R> *src_, C2<R> *dst, i
 
 template <typename R, int E, int RL, int GS, int RS, int NTH>
 __device__ __forceinline__ void block_store_rows(const C2<R> *src, C2<R> *dst_, int tid) {
+    if constexpr (PAIR_ROWS<R, RL, GS, RS>) {
+        using F4 = float __attribute__((ext_vector_type(4)));
+        static_assert(E % RL == 0, "whole rows");
+        constexpr int RP = (RL + 1) / 2, EP = E / RL * RP;
+        constexpr int T = (EP + NTH - 1) / NTH;
+        ITSE_GLOBAL F4 *d4 = (ITSE_GLOBAL F4 *)gmem(dst_);
+        const F4 *s4 = (const F4 *)src;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int e = tid + t * NTH;
+            if (EP % NTH == 0 || e < EP) d4[(e / RP) * (GS / 2) + e % RP] = s4[(e / RP) * (RS / 2) + e % RP];
+        }
+        return;
+    }
     ITSE_GLOBAL C2<R> *dst = gmem(dst_);
     constexpr int T = (E + NTH - 1) / NTH;
 #pragma unroll
@@ -391,7 +436,7 @@ __global__ void __launch_bounds__((Geo<R, N, V>::NTP)) __attribute__((amdgpu_wav
 k_plane_fwd(const JobRef *__restrict__ jobs) {
     using G = Geo<R, N, V>;
     constexpr int S = G::S, M = G::M, H = G::H, HP = G::HP, LSZ = G::LSZ, PPW = G::PPW, CPW = G::CPW;
-    __shared__ C2<R> buf[G::PLANE_ELEMS];
+    __shared__ __attribute__((aligned(16))) C2<R> buf[G::PLANE_ELEMS];
     __shared__ C2<R> tw[N];
     const JobRef job = jobs[blockIdx.y];
     const LatDev &L = *job.lat;
@@ -483,7 +528,7 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
                                                               int moments, C2<R> *__restrict__ out) {
     using G = Geo<R, N, V>;
     constexpr int S = G::S, M = G::M, H = G::H, W = G::W, CS = G::CS, LPW = G::LPWC, NTC = G::NTC;
-    __shared__ C2<R> buf[N * CS];
+    __shared__ __attribute__((aligned(16))) C2<R> buf[N * CS];
     __shared__ C2<R> tw[N];
     __shared__ double ktab[N];
     __shared__ double red[NQC * (NTC / 64)];
@@ -505,7 +550,50 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
     const size_t sub = (size_t)N * M * HS;  // one sub-spectrum
     // load S sub-spectra values (all loads of the thread first), combine over r ->
     // S full-y columns ky = ky' + M q
-    {
+    if constexpr (sizeof(R) == 4 && W % 2 == 0) {
+        // FP32: two kz per thread, one 16-byte load per sub-spectrum (rows are
+        // padded, so the pair at kz = N/2 stays in the row; its upper half is
+        // padding and is replaced by zero)
+        constexpr int W2 = W / 2;
+        constexpr int T = (N * W2 + NTC - 1) / NTC;
+        using F4 = float __attribute__((ext_vector_type(4)));
+        F4 v[T][S];
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int e = tid + t * NTC;
+            const int xx = e / W2, kz = kz0 + 2 * (e % W2);
+            const bool ok = ((N * W2) % NTC == 0 || e < N * W2) && kz < H;
+            const size_t base = ((size_t)xx * M + kyp) * HS + kz;
+#pragma unroll
+            for (int rr = 0; rr < S; ++rr) {
+                v[t][rr] = ok ? *(const ITSE_GLOBAL F4 *)(spec + rr * sub + base) : F4{0.f, 0.f, 0.f, 0.f};
+                if (kz + 1 >= H) {
+                    v[t][rr].z = 0.f;
+                    v[t][rr].w = 0.f;
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int e = tid + t * NTC;
+            if ((N * W2) % NTC != 0 && e >= N * W2) continue;
+            const int xx = e / W2, w = 2 * (e % W2);
+            C2<R> a[S], b[S];
+#pragma unroll
+            for (int rr = 0; rr < S; ++rr) {
+                a[rr] = C2<R>{v[t][rr].x, v[t][rr].y};
+                b[rr] = C2<R>{v[t][rr].z, v[t][rr].w};
+                if (rr > 0) {
+                    a[rr] = cmul(a[rr], tw[rr * kyp]);
+                    b[rr] = cmul(b[rr], tw[rr * kyp]);
+                }
+            }
+            Dft<S, -1, R>::run(a);
+            Dft<S, -1, R>::run(b);
+#pragma unroll
+            for (int q = 0; q < S; ++q) *(F4 *)&buf[xx * CS + q * W + w] = F4{a[q].x, a[q].y, b[q].x, b[q].y};
+        }
+    } else {
         constexpr int T = (N * W + NTC - 1) / NTC;
         C2<R> v[T][S];
 #pragma unroll
@@ -646,6 +734,36 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
     }
     if (mom) block_sums<NQC, NTC>(acc, L.part_cols + ((size_t)i * L.nb_cols + blk) * NQC, red);
     __syncthreads();
+    if constexpr (sizeof(R) == 4 && W % 2 == 0) {
+        // FP32: two kz per thread, 16-byte stores (8 bytes at kz = N/2)
+        using F4 = float __attribute__((ext_vector_type(4)));
+        constexpr int W2 = W / 2;
+        for (int e = tid; e < N * W2; e += NTC) {
+            const int xx = e / W2, w = 2 * (e % W2), kz = kz0 + w;
+            if (kz >= H) continue;
+            C2<R> a[S], b[S];
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const F4 f = *(const F4 *)&buf[xx * CS + q * W + w];
+                a[q] = C2<R>{f.x, f.y};
+                b[q] = C2<R>{f.z, f.w};
+            }
+            Dft<S, +1, R>::run(a);
+            Dft<S, +1, R>::run(b);
+            const size_t base = ((size_t)xx * M + kyp) * HS + kz;
+#pragma unroll
+            for (int rr = 0; rr < S; ++rr) {
+                C2<R> x0 = a[rr], x1 = b[rr];
+                if (rr > 0) {
+                    x0 = cmul(x0, cconj(tw[rr * kyp]));
+                    x1 = cmul(x1, cconj(tw[rr * kyp]));
+                }
+                if (kz + 1 < H) *(ITSE_GLOBAL F4 *)(spec + rr * sub + base) = F4{x0.x, x0.y, x1.x, x1.y};
+                else spec[rr * sub + base] = x0;
+            }
+        }
+        return;
+    }
     for (int e = tid; e < N * W; e += NTC) {
         const int xx = e / W, w = e % W, kz = kz0 + w;
         if (kz >= H) continue;
@@ -674,7 +792,7 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     using G = Geo<R, N, V>;
     constexpr int S = G::S, M = G::M, H = G::H, HP = G::HP, LSZ = G::LSZ, PPW = G::PPW, CPW = G::CPW;
     constexpr int NTP = G::NTP;
-    __shared__ C2<R> buf[G::PLANE_ELEMS];
+    __shared__ __attribute__((aligned(16))) C2<R> buf[G::PLANE_ELEMS];
     __shared__ C2<R> tw[N];
     __shared__ double red[NQR * (NTP / 64)];
     const JobRef job = jobs[blockIdx.y];
