@@ -1130,11 +1130,16 @@ extern "C" itse_status itse_profile_step(itse_lattice *L, int nsteps, double *ms
     if (!L || !npass || (*npass > 0 && !ms_out)) return fail(ITSE_EINVAL, "null argument");
     if (nsteps < 1) return fail(ITSE_EINVAL, "nsteps < 1");
     Group g = single_group(L);
+    // passes a step of these options does not launch are reported as 0
+    bool launched[NPASS];
+    for (int p = 0; p < NPASS; ++p)
+        launched[p] = !((p == 3 && !(g.needs & NEED_PROJECT)) || (p == 4 && !(g.needs & NEED_GRAM)));
     std::vector<hipEvent_t> ev((size_t)nsteps * (NPASS + 1));
     for (auto &e : ev) HIPCHK(hipEventCreate(&e));
     for (int s = 0; s < nsteps; ++s) {
         HIPCHK(hipEventRecord(ev[(size_t)s * (NPASS + 1)], L->stream));
         for (int p = 0; p < NPASS; ++p) {
+            if (!launched[p]) continue;
             hipError_t e = L->d.precision == ITSE_FP32 ? launch_pass<float>(g, p, L->stream)
                                                        : launch_pass<double>(g, p, L->stream);
             if (e != hipSuccess) return fail(ITSE_EDEVICE, "pass %d: %s", p, hipGetErrorString(e));
@@ -1146,10 +1151,15 @@ extern "C" itse_status itse_profile_step(itse_lattice *L, int nsteps, double *ms
     const int cap = *npass;
     for (int p = 0; p < NPASS && p < cap; ++p) {
         double acc = 0.0;
-        for (int s = 0; s < nsteps; ++s) {
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, ev[(size_t)s * (NPASS + 1) + p], ev[(size_t)s * (NPASS + 1) + p + 1]));
-            acc += ms;
+        if (launched[p]) {
+            int prev = p;  // the event recorded before this pass
+            while (prev > 0 && !launched[prev - 1]) --prev;
+            for (int s = 0; s < nsteps; ++s) {
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, ev[(size_t)s * (NPASS + 1) + prev],
+                                           ev[(size_t)s * (NPASS + 1) + p + 1]));
+                acc += ms;
+            }
         }
         ms_out[p] = acc / nsteps;
     }
