@@ -337,6 +337,29 @@ def main():
     extra["k1_ms_per_step"] = secs1 * 1000.0 / steps1
     extra["k1_hbm_frac"] = sum(pb1.values()) / (secs1 / steps1) / 1e9 / HBM_PEAK_GBS
     extra["k1_passes_ms"] = prof1
+    # snapshot-overlap extraction on the one-state lattice: keeping a snapshot,
+    # and forming the three estimates with their energies (second call timed; the
+    # first one creates the analysis lattice)
+    lat1.snapshot()
+    lat1.step(16)
+    lat1.snapshot()
+    lat1.step(16)
+    lat1.extract()
+    lat1.sync()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        lat1.snapshot()
+    lat1.sync()
+    push_ms = (time.perf_counter() - t0) * 100.0
+    lat1.step(16)
+    lat1.snapshot()
+    lat1.step(16)
+    lat1.sync()
+    t0 = time.perf_counter()
+    snap_obs = lat1.extract()
+    extract_ms = (time.perf_counter() - t0) * 1000.0
+    extra["snapshot_overlap"] = {"push_ms": push_ms, "extract_ms": extract_ms,
+                                 "estimates": len(snap_obs)}
     lat1.close()
     if not args.no_fp64:
         p64, v64, st64 = build_workload(n, fp32=False)

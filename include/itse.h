@@ -190,6 +190,37 @@ itse_status itse_spectrum(itse_lattice *lat, int i, void *out_device);
  * Synchronises. */
 itse_status itse_polish(itse_lattice *lat, int i, itse_obs *out);
 
+/* ---- Snapshot-overlap extraction of excited states ----------------------
+ * The paper's procedure (section "The iterative procedure"): while state 0
+ * evolves, snapshots of it are kept; the latest wave-function estimates the
+ * ground state, and each earlier snapshot, newest first, with its projections
+ * on the estimates found so far removed and then normalised, estimates the next
+ * state.  The library keeps the ITSE_SNAPSHOTS latest snapshots of state 0. */
+#define ITSE_SNAPSHOTS 2
+
+/* Copies the current state 0 into the snapshot ring; when the ring is full the
+ * oldest snapshot is dropped.  The first call allocates the ring (ITSE_SNAPSHOTS
+ * arrays of N^3 values in the lattice precision, through the lattice's
+ * allocator; not part of itse_footprint_bytes).  Asynchronous on the lattice
+ * stream.  Errors: ITSE_ENOMEM. */
+itse_status itse_snapshot_push(itse_lattice *lat);
+
+/* Number of snapshots held, 0..ITSE_SNAPSHOTS. */
+itse_status itse_snapshot_count(const itse_lattice *lat, int *count);
+
+/* Drops the snapshots (the ring stays allocated). */
+itse_status itse_snapshot_clear(itse_lattice *lat);
+
+/* Forms the 1 + count estimates from the current state 0 and the snapshots and
+ * writes their observables (FP64 Rayleigh quotients, norms, moments, parity
+ * weights) to out[0 .. 1 + count); *n_out receives 1 + count.  If states_out is
+ * not NULL, estimate e is written at states_out + e N^3 values of `dtype`
+ * (ITSE_DTYPE_F32 or ITSE_DTYPE_F64), in host or device memory per on_device.
+ * The lattice's own states and snapshots are not changed.  Synchronises.
+ * Errors: ITSE_ENONFINITE if a snapshot lies in the span of the later ones. */
+itse_status itse_snapshot_extract(itse_lattice *lat, itse_obs *out, int *n_out, void *states_out, int dtype,
+                                  int on_device);
+
 /* Per-pass timing: `nsteps` steps launched eagerly with HIP events recorded
  * between consecutive kernel launches on the lattice stream.  On input *npass is
  * the capacity of ms_out; on output the number of passes per step, with

@@ -173,6 +173,17 @@ def orthonormalise(states) -> np.ndarray:
     return psi
 
 
+def snapshot_extract(L: Lattice, current: np.ndarray, snapshots, v: np.ndarray):
+    """Ground- and excited-state estimates by the snapshot-overlap procedure
+    (section "The iterative procedure"): the latest wave-function estimates the
+    ground state; each earlier snapshot in turn, newest first, with its
+    projections on all estimates found so far removed and normalised, estimates
+    the next state.  `snapshots` are ordered newest first.  Returns
+    (estimates [1 + len(snapshots), N, N, N], their observables)."""
+    est = orthonormalise([current] + list(snapshots))
+    return est, observe(L, est, v)
+
+
 def step(L: Lattice, states, v: np.ndarray, nsteps: int, step0: int = 0, ortho_every: int = 1,
          parity: Optional[Sequence[int]] = None, axes: Optional[Sequence[int]] = None,
          record: bool = True):

@@ -106,6 +106,10 @@ def load():
         "itse_spectrum": ([vp, ip, vp], ip),
         "itse_polish": ([vp, ip, P(Obs)], ip),
         "itse_sync": ([vp], ip),
+        "itse_snapshot_push": ([vp], ip),
+        "itse_snapshot_count": ([vp, P(ip)], ip),
+        "itse_snapshot_clear": ([vp], ip),
+        "itse_snapshot_extract": ([vp, P(Obs), P(ip), vp, ip, ip], ip),
         "itse_profile_step": ([vp, ip, P(dp), P(ip), ctypes.c_char_p, ctypes.c_size_t], ip),
         "itse_batch_create": ([ip, P(vp), vp, P(vp)], ip),
         "itse_batch_step": ([vp, ip], ip),

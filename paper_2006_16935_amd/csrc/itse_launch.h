@@ -180,6 +180,31 @@ hipError_t Launch<R>::project_gram(int n, int kmax, const JobRef *lats, int nlat
                                    hipStream_t s) {
     if (nlats <= 0) return hipSuccess;
     const dim3 grid(n * pg_chunks(n), nlats);
+    if (kmax <= 4 && n / VLEN<R> <= 64) {
+        // 16-byte form (rows of at most 64 vectors, up to four states)
+        auto vec = [&](auto nc) -> hipError_t {
+            constexpr int NN = decltype(nc)::value;
+            if constexpr (NN % VLEN<R> == 0 && NN / VLEN<R> <= 64) {
+                if (kmax <= 1)
+                    hipLaunchKernelGGL((k_project_gram_vec<R, 1, NN>), grid, dim3(NT), 0, s, lats, force, which);
+                else if (kmax <= 2)
+                    hipLaunchKernelGGL((k_project_gram_vec<R, 2, NN>), grid, dim3(NT), 0, s, lats, force, which);
+                else if (kmax <= 3)
+                    hipLaunchKernelGGL((k_project_gram_vec<R, 3, NN>), grid, dim3(NT), 0, s, lats, force, which);
+                else
+                    hipLaunchKernelGGL((k_project_gram_vec<R, 4, NN>), grid, dim3(NT), 0, s, lats, force, which);
+                return hipGetLastError();
+            }
+            return hipErrorInvalidValue;
+        };
+        switch (n) {
+#define ITSE_CASE(NN) \
+    case NN: return vec(std::integral_constant<int, NN>{});
+            ITSE_FOR_EACH_N(ITSE_CASE)
+#undef ITSE_CASE
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (kmax <= 1) hipLaunchKernelGGL((k_project_gram<R, 1>), grid, dim3(NT), 0, s, lats, force, which);
     else if (kmax <= 2) hipLaunchKernelGGL((k_project_gram<R, 2>), grid, dim3(NT), 0, s, lats, force, which);
     else if (kmax <= 3) hipLaunchKernelGGL((k_project_gram<R, 3>), grid, dim3(NT), 0, s, lats, force, which);

@@ -1107,6 +1107,148 @@ __global__ void __launch_bounds__(NT) k_project_gram(const JobRef *__restrict__ 
     block_sums<NGK, NT>(acc, L.part_gram + (size_t)blockIdx.x * NG, red);
 }
 
+// ---------------------------------------------------------------------------
+// The same projection and Gram sums with 16-byte accesses, for rows of at most
+// 64 vectors (GPR = N / VLEN groups of VLEN consecutive z per row).  Workgroup
+// (plane x, chunk) with x <= mirror(x) takes the row pairs {A = (x, y),
+// B = (xm, ym)} of its rows.  Lane g of a row slot holds group g of A and group
+// GPR - 1 - g of B (group g when z is not reflected), so the mirror of each site
+// is in the lane's other vector, except for origin centring (z -> -z mod N), where
+// element 0 pairs with element 0 of the neighbouring lane's other vector.  A row
+// pair is read completely before it is written; a pair that is its own mirror
+// (x = xm, y = ym) is written and summed on its A side only.
+// ---------------------------------------------------------------------------
+template <typename R, int KM, int N>
+__global__ void __launch_bounds__(NT) k_project_gram_vec(const JobRef *__restrict__ lats, int force, int which) {
+    constexpr int NG = MAXK * (MAXK + 1) / 2;
+    constexpr int NGK = KM * (KM + 1) / 2;
+    constexpr int VL = VLEN<R>;
+    constexpr int GPR = N / VL;                 // vectors per row
+    constexpr int RPW = 64 / GPR;               // row slots per wave
+    constexpr int NWV = NT / 64;
+    constexpr int RB = 2;                       // row pairs in flight per slot
+    static_assert(N % VL == 0 && GPR <= 64, "rows of at most 64 vectors");
+    __shared__ double red[NGK * (NT / 64)];
+    const LatDev &L = *lats[blockIdx.y].lat;
+    const int K = L.nstates;
+    const bool ortho = force || (K > 1 && L.ortho_every > 0 && ((L.step + 1) % L.ortho_every) == 0);
+    const bool do_proj = !force && L.proj_mode == 1;
+    if (!(ortho || (!force && L.proj_mode != 0)) || K > KM) return;  // finalize reads nothing then
+    const int center = L.center;
+    const int chunks = L.pg_chunks;
+    const int x = blockIdx.x / chunks, ch = blockIdx.x % chunks;
+    const int axes = do_proj ? L.proj_axes : 0;
+    const int xm = (axes & 1) ? mirror_idx(x, N, center) : x;
+    const bool zr = (axes & 4) != 0;
+    const bool origin_z = zr && center != ITSE_CENTER_CELL;
+    double acc[NGK];
+#pragma unroll
+    for (int g = 0; g < NGK; ++g) acc[g] = 0.0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int slot = lane / GPR, g = lane % GPR;
+    const int gb = zr ? GPR - 1 - g : g;
+    const int src_prev = slot * GPR + (g + GPR - 1) % GPR;  // lane holding group g - 1
+    const int src_next = slot * GPR + (g + 1) % GPR;        // lane holding group g + 1
+    ITSE_GLOBAL R *uj[KM];
+    R sg[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        uj[j] = gmem((R *)state_buf(L, L.step, which, j < K ? j : 0));
+        sg[j] = (do_proj && j < K) ? (R)L.psign[j] : (R)0;
+    }
+    const int rpc = (N + chunks - 1) / chunks;
+    const int y0 = ch * rpc, y1 = y0 + rpc < N ? y0 + rpc : N;
+    const bool active = xm >= x && slot < RPW;
+    // row slots of the workgroup step through the chunk's rows together (the
+    // shuffles below need every lane of the wave)
+    constexpr int SLOTS = NWV * RPW;
+    for (int yb = y0; yb < y1; yb += SLOTS * RB) {
+        Vec<R> va[RB][KM], vb[RB][KM];
+        size_t oa[RB], ob[RB];
+        bool ok[RB], self[RB];
+#pragma unroll
+        for (int t = 0; t < RB; ++t) {
+            const int y = yb + (t * NWV + wv) * RPW + slot;
+            const int ym = (axes & 2) ? mirror_idx(y < N ? y : 0, N, center) : y;
+            ok[t] = active && y < y1 && (xm != x || y <= ym);
+            self[t] = xm == x && y == ym;
+            oa[t] = ok[t] ? ((size_t)x * N + y) * N + (size_t)g * VL : 0;
+            ob[t] = ok[t] ? ((size_t)xm * N + ym) * N + (size_t)gb * VL : 0;
+#pragma unroll
+            for (int j = 0; j < KM; ++j) {
+                if (ok[t] && j < K) {
+                    va[t][j] = *(const ITSE_GLOBAL Vec<R> *)(uj[j] + oa[t]);
+                    vb[t][j] = *(const ITSE_GLOBAL Vec<R> *)(uj[j] + ob[t]);
+                } else {
+                    va[t][j] = Vec<R>{};
+                    vb[t][j] = Vec<R>{};
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RB; ++t) {
+            double da[KM][VL], db[KM][VL];
+#pragma unroll
+            for (int j = 0; j < KM; ++j) {
+                // mirror values of this lane's A and B sites
+                R ma[VL], mb[VL];
+                if (origin_z) {
+                    const R b0 = __shfl(vb[t][j][0], src_prev, 64);
+                    const R a0 = __shfl(va[t][j][0], src_next, 64);
+                    ma[0] = b0;
+                    mb[0] = a0;
+#pragma unroll
+                    for (int k = 1; k < VL; ++k) {
+                        ma[k] = vb[t][j][VL - k];
+                        mb[k] = va[t][j][VL - k];
+                    }
+                } else if (zr) {
+#pragma unroll
+                    for (int k = 0; k < VL; ++k) {
+                        ma[k] = vb[t][j][VL - 1 - k];
+                        mb[k] = va[t][j][VL - 1 - k];
+                    }
+                } else {
+#pragma unroll
+                    for (int k = 0; k < VL; ++k) {
+                        ma[k] = vb[t][j][k];
+                        mb[k] = va[t][j][k];
+                    }
+                }
+                Vec<R> pa = va[t][j], pb = vb[t][j];
+                if (sg[j] != (R)0) {
+#pragma unroll
+                    for (int k = 0; k < VL; ++k) {
+                        pa[k] = (R)0.5 * (va[t][j][k] + sg[j] * ma[k]);
+                        pb[k] = (R)0.5 * (vb[t][j][k] + sg[j] * mb[k]);
+                    }
+                    if (ok[t]) {
+                        *(ITSE_GLOBAL Vec<R> *)(uj[j] + oa[t]) = pa;
+                        if (!self[t]) *(ITSE_GLOBAL Vec<R> *)(uj[j] + ob[t]) = pb;
+                    }
+                }
+                const bool use_b = ok[t] && !self[t];
+#pragma unroll
+                for (int k = 0; k < VL; ++k) {
+                    da[j][k] = ok[t] && j < K ? (double)pa[k] : 0.0;
+                    db[j][k] = use_b && j < K ? (double)pb[k] : 0.0;
+                }
+            }
+            int q = 0;
+#pragma unroll
+            for (int l = 0; l < KM; ++l)
+#pragma unroll
+                for (int j = 0; j <= l; ++j) {
+#pragma unroll
+                    for (int k = 0; k < VL; ++k) acc[q] += da[j][k] * da[l][k] + db[j][k] * db[l][k];
+                    ++q;
+                }
+        }
+    }
+    // slot layout l (l + 1) / 2 + j, the same for every KM
+    block_sums<NGK, NT>(acc, L.part_gram + (size_t)blockIdx.x * NG, red);
+}
+
 // out_i = sum_j coef[j][i] u_j (materialise the current state i), FP64 combination.
 template <typename R>
 __global__ void __launch_bounds__(NT) k_combine(const JobRef *__restrict__ jobs, void *const *outs) {

@@ -67,6 +67,10 @@ struct itse_lattice {
     hipGraphExec_t graphN = nullptr;
     int graph_needs = -1;              // optional passes captured in graph1 / graphN
     itse_lattice *shadow = nullptr;    // FP64 twin for polish
+    void *snap[ITSE_SNAPSHOTS] = {};   // snapshot ring of state 0
+    void **snap_ptr_dev = nullptr;     // [ITSE_SNAPSHOTS] device copies of snap[]
+    int snap_count = 0, snap_newest = -1;
+    itse_lattice *snapx = nullptr;     // estimates of the snapshot-overlap extraction
     void *cur_raw(int i) const { return itse::state_buf(host, steps_host, 0, i); }
     void *stage_buf(size_t bytes);
     ~itse_lattice();

@@ -657,6 +657,7 @@ extern "C" itse_status itse_destroy(itse_lattice *L) {
     if (L->graphN) (void)hipGraphExecDestroy(L->graphN);
     if (L->cap_stream) (void)hipStreamDestroy(L->cap_stream);
     if (L->shadow) itse_destroy(L->shadow);
+    if (L->snapx) itse_destroy(L->snapx);
     lat_free_all(L);
     delete L;
     return ITSE_OK;
@@ -1102,6 +1103,95 @@ extern "C" itse_status itse_polish(itse_lattice *L, int i, itse_obs *out) {
     st = itse_evaluate(S, 1);
     if (st) return st;
     return itse_observe(S, 0, out);
+}
+
+// ------------------------------------------------------------------------------------
+// Snapshot-overlap extraction of excited states (section "The iterative procedure")
+// ------------------------------------------------------------------------------------
+extern "C" itse_status itse_snapshot_push(itse_lattice *L) {
+    if (!L) return fail(ITSE_EINVAL, "null lattice");
+    const size_t n3 = (size_t)L->d.n * L->d.n * L->d.n;
+    if (!L->snap[0]) {
+        void *ptrs[ITSE_SNAPSHOTS];
+        for (int k = 0; k < ITSE_SNAPSHOTS; ++k) {
+            L->snap[k] = lat_alloc(L, n3 * real_bytes(L->d.precision));
+            if (!L->snap[k]) return fail(ITSE_ENOMEM, "snapshot ring");
+            ptrs[k] = L->snap[k];
+        }
+        L->snap_ptr_dev = (void **)lat_alloc(L, sizeof ptrs);
+        if (!L->snap_ptr_dev) return fail(ITSE_ENOMEM, "snapshot ring");
+        HIPCHK(hipMemcpyAsync(L->snap_ptr_dev, ptrs, sizeof ptrs, hipMemcpyHostToDevice, L->stream));
+    }
+    // the slot after the newest one (the oldest once the ring is full)
+    const int slot = (L->snap_newest + 1) % ITSE_SNAPSHOTS;
+    hipError_t e = L->d.precision == ITSE_FP32
+                       ? Launch<float>::combine(L->d.n, L->jobs_dev, 1, L->snap_ptr_dev + slot, L->stream)
+                       : Launch<double>::combine(L->d.n, L->jobs_dev, 1, L->snap_ptr_dev + slot, L->stream);
+    if (e != hipSuccess) return fail(ITSE_EDEVICE, "snapshot: %s", hipGetErrorString(e));
+    L->snap_newest = slot;
+    L->snap_count = std::min(L->snap_count + 1, ITSE_SNAPSHOTS);
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_snapshot_count(const itse_lattice *L, int *count) {
+    if (!L || !count) return fail(ITSE_EINVAL, "null argument");
+    *count = L->snap_count;
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_snapshot_clear(itse_lattice *L) {
+    if (!L) return fail(ITSE_EINVAL, "null lattice");
+    L->snap_count = 0;
+    L->snap_newest = -1;
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_snapshot_extract(itse_lattice *L, itse_obs *out, int *n_out, void *states_out, int dtype,
+                                             int on_device) {
+    if (!L || !out || !n_out) return fail(ITSE_EINVAL, "null argument");
+    if (states_out && dtype != ITSE_DTYPE_F32 && dtype != ITSE_DTYPE_F64) return fail(ITSE_EINVAL, "dtype");
+    const int ne = 1 + L->snap_count;
+    // a lattice of the same description holding the current state and the
+    // snapshots, newest first, as its states 0 .. ne-1
+    if (L->snapx && L->snapx->d.nstates != ne) {
+        itse_destroy(L->snapx);
+        L->snapx = nullptr;
+    }
+    if (!L->snapx) {
+        itse_desc d = L->d;
+        d.nstates = ne;
+        itse_status st = itse_create(&d, L->stream, L->alloc, L->freefn, L->alloc_user, &L->snapx);
+        if (st) return st;
+    }
+    itse_lattice *X = L->snapx;
+    itse_status st = itse_set_stream(X, L->stream);
+    if (st) return st;
+    const int wdt = L->d.precision == ITSE_FP32 ? ITSE_DTYPE_F32 : ITSE_DTYPE_F64;
+    if ((st = itse_set_potential(X, L->host.v, wdt, 1))) return st;
+    hipError_t e = L->d.precision == ITSE_FP32
+                       ? Launch<float>::combine(L->d.n, L->jobs_dev, 1, L->tmp_ptrs_dev, L->stream)
+                       : Launch<double>::combine(L->d.n, L->jobs_dev, 1, L->tmp_ptrs_dev, L->stream);
+    if (e != hipSuccess) return fail(ITSE_EDEVICE, "combine: %s", hipGetErrorString(e));
+    if ((st = itse_set_state(X, 0, L->tmp, wdt, 1))) return st;
+    for (int k = 0; k < L->snap_count; ++k) {
+        const int slot = ((L->snap_newest - k) % ITSE_SNAPSHOTS + ITSE_SNAPSHOTS) % ITSE_SNAPSHOTS;
+        if ((st = itse_set_state(X, 1 + k, L->snap[slot], wdt, 1))) return st;
+    }
+    // Gram-Schmidt in that order: estimate e is snapshot e minus its projections
+    // on estimates 0 .. e-1, normalised
+    for (int k = 0; k < ne; ++k)
+        if ((st = itse_orthogonalise(X, k))) return st;
+    if ((st = itse_evaluate(X, 1))) return st;
+    for (int k = 0; k < ne; ++k)
+        if ((st = itse_observe(X, k, &out[k]))) return st;
+    *n_out = ne;
+    if (states_out) {
+        const size_t n3 = (size_t)L->d.n * L->d.n * L->d.n;
+        const size_t sw = dtype == ITSE_DTYPE_F32 ? 4 : 8;
+        for (int k = 0; k < ne; ++k)
+            if ((st = itse_get_state(X, k, (char *)states_out + (size_t)k * n3 * sw, dtype, on_device))) return st;
+    }
+    return ITSE_OK;
 }
 
 // ------------------------------------------------------------------------------------

@@ -231,6 +231,38 @@ class Lattice:
     def sync(self):
         check(self._L.itse_sync(self.h))
 
+    # -- snapshot-overlap extraction (itse_snapshot_*) ---------------------------------
+    def snapshot(self):
+        """Keep the current state 0 as the newest snapshot (the ring holds two)."""
+        check(self._L.itse_snapshot_push(self.h))
+
+    @property
+    def snapshot_count(self) -> int:
+        c = ctypes.c_int()
+        check(self._L.itse_snapshot_count(self.h, ctypes.byref(c)))
+        return c.value
+
+    def clear_snapshots(self):
+        check(self._L.itse_snapshot_clear(self.h))
+
+    def extract(self, states: bool = False, dtype=np.float64):
+        """Estimates from the current state 0 and the snapshots, newest first:
+        list of observable dicts, and with states=True also the estimates as an
+        array [1 + snapshot_count, N, N, N] of `dtype`."""
+        outs = (_lib.Obs * 3)()
+        n_out = ctypes.c_int()
+        arr = None
+        ptr = None
+        code = _lib.DTYPE_F64
+        if states:
+            n = self.n
+            arr = np.empty((1 + self.snapshot_count, n, n, n), dtype=dtype)
+            code = _lib.DTYPE_F32 if arr.dtype == np.float32 else _lib.DTYPE_F64
+            ptr = arr.ctypes.data_as(ctypes.c_void_p)
+        check(self._L.itse_snapshot_extract(self.h, outs, ctypes.byref(n_out), ptr, code, 0))
+        obs = [outs[k].as_dict() for k in range(n_out.value)]
+        return (obs, arr) if states else obs
+
     def profile_step(self, nsteps: int = 5):
         """Mean duration (ms) of each pass of a step, measured with HIP events."""
         import json

@@ -143,6 +143,43 @@ def test_projection_modes(itse, orc, n, prec, parity, axes, ortho):
     lat.close()
 
 
+@pytest.mark.parametrize("n,prec,parity,axes", [
+    (12, "fp32", (1, -1, 0), (7, 7, 7)),      # three vectors per row
+    (16, "fp64", (-1, 1, 1), (4, 4, 4)),      # z alone (element 0 pairs across lanes)
+    (48, "fp32", (0, 1, -1), (5, 5, 5)),      # x and z
+    (24, "fp64", (1, -1, -1), (3, 3, 3)),     # x and y, z kept
+    (192, "fp64", (1, -1, 0), (7, 7, 7)),     # rows longer than one wave of vectors
+])
+def test_projection_origin_axes(itse, orc, n, prec, parity, axes):
+    """Reflections about the origin (z -> -z mod N pairs element 0 of one vector with
+    the neighbouring vector) on shared axes, with Gram-Schmidt every step: energies,
+    parity weights and states follow the oracle."""
+    steps = 6
+    a = 0.25
+    lat = _lat(itse, n, prec, 0, kin=2, nstates=3, center="origin", a=a, mass=1.1)
+    dt = np.float32 if prec == "fp32" else np.float64
+    v = synth.potential_harmonic(n, a, "origin", 0.5).astype(dt)
+    states = synth.random_states(n, 3, seed=70 + n, dtype=dt)
+    lat.set_potential(v)
+    for i, s in enumerate(states):
+        lat.set_state(i, s)
+    lat.set_options(ortho_every=1, moments=True, parity=parity, axes=axes)
+    lat.step(steps)
+    hist = lat.history(steps)
+    ostates, ohist = orc.step(_olat(orc, lat), [s.astype(np.float64) for s in states],
+                              v.astype(np.float64), steps, ortho_every=1, parity=parity, axes=axes)
+    etol = 1e-10 if prec == "fp64" else 1e-5
+    for s in range(steps):
+        for i in range(3):
+            for f in ("energy", "norm2", "parity_even"):
+                g, r = hist[s][i][f], ohist[s][i][f]
+                assert abs(g - r) <= etol * max(1.0, abs(r)), (s, i, f, g, r)
+    stol = 1e-10 if prec == "fp64" else 1e-4
+    for i in range(3):
+        assert _rel(lat.get_state(i), ostates[i]) < stol
+    lat.close()
+
+
 def test_precision_workload_first_steps(itse, orc):
     """The 256^3 FP32 workload the benchmark times, in its default schedule: the
     energies of the first steps match the FP64 oracle on the same FP32 inputs."""

@@ -207,3 +207,48 @@ def test_chunked_steps_equal_one_run(orc):
     a, _ = orc.step(L, s0, v, 7, ortho_every=3, record=False)
     b, _ = orc.step(L, a, v, 5, step0=7, ortho_every=3, record=False)
     assert np.array_equal(full, b)
+
+
+def test_snapshot_extraction_plane_waves(orc):
+    """Snapshot-overlap extraction (section "The iterative procedure") pinned by a
+    closed form: with V = 0 the map multiplies each plane wave by
+    lambda(k) = 1 - dtau T(k), so a mix of three orthonormal cosine waves stays a
+    mix whose coefficients at step n are a_k lambda_k^n.  Gram-Schmidt of the
+    coefficient vectors (latest, then earlier snapshots) gives the estimates and
+    their energies sum_k q_k^2 T(k) exactly; the oracle, stepping the full
+    lattice with its FFTs, must reproduce both."""
+    n, a, m, dtau = 8, 0.5, 1.0, 0.03            # dtau max T = 1.78, inside the stable range
+    L = orc.lattice(n, a, m, dtau, orc.KIN_NR_CONT, True, "cell")
+    x = np.arange(n)
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    waves, T = [], []
+    for mv in [(0, 0, 0), (1, 0, 0), (1, 1, 0)]:
+        w = np.cos(2 * np.pi * (mv[0] * X + mv[1] * Y + mv[2] * Z) / n)
+        waves.append(w / np.sqrt((w * w).sum()))
+        k2 = sum((2 * np.pi * c / n) ** 2 for c in mv)
+        T.append(k2 / (2 * a * a * m))
+    T = np.array(T)
+    coef0 = np.array([1.0, 0.8, 0.6])
+    psi0 = sum(c * w for c, w in zip(coef0, waves))
+    v = np.zeros((n, n, n))
+    marks = [5, 20, 50]                    # snapshot steps, the last one is "current"
+    snaps, state, done = [], psi0[None], 0
+    for mk in marks:
+        state, _ = orc.step(L, state, v, mk - done, step0=done, record=False)
+        done = mk
+        snaps.append(state[0].copy())
+    est, obs = orc.snapshot_extract(L, snaps[-1], snaps[-2::-1], v)
+    lam = 1.0 - dtau * T
+    cols = [coef0 * lam ** mk for mk in marks[::-1]]     # latest first
+    q = []
+    for c in cols:
+        c = c.copy()
+        for b in q:
+            c -= (b @ c) * b
+        q.append(c / np.linalg.norm(c))
+    for i in range(3):
+        ref = sum(q[i][k] * waves[k] for k in range(3))
+        assert np.abs(est[i] - ref).max() < 1e-12
+        assert abs(obs[i]["energy"] - (q[i] ** 2) @ T) < 1e-12
+    # the estimates approach the eigenstates in order of energy
+    assert obs[0]["energy"] < obs[1]["energy"] < obs[2]["energy"]
