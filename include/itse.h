@@ -56,9 +56,12 @@ typedef enum {
     ITSE_ENOTFOUND = -7    /* no such request / no result yet */
 } itse_status;
 
-/* Kinetic terms (the paper's KINTERM 1..3, plus the relativistic analogue of
+/* Kinetic terms (the paper's KINTERM 0..3, plus the relativistic analogue of
  * H_K^(1) the paper calls straightforward in section "Kinetic terms"). */
 typedef enum {
+    ITSE_KIN_FDTD = 0,     /* H_K^(0) (equation HK0): 7-point finite differences  */
+                           /* / (2 A^2 M), psi = 0 outside the N^3 box (Dirichlet);*/
+                           /* one stencil pass per step instead of the transforms  */
     ITSE_KIN_NR_CONT = 1,  /* H_K^(1): sum k_l^2 / (2 A^2 M)                     */
     ITSE_KIN_NR_LAT = 2,   /* H_K^(2): 4 sum sin^2(k_l/2) / (2 A^2 M)             */
     ITSE_KIN_REL_LAT = 3,  /* H_K^(3): sqrt(p^2 + M^2), p^2 = 4/A^2 sum sin^2     */

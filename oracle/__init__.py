@@ -32,7 +32,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "itse_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-KIN_NR_CONT, KIN_NR_LAT, KIN_REL_LAT, KIN_REL_CONT = 1, 2, 3, 4
+KIN_FDTD, KIN_NR_CONT, KIN_NR_LAT, KIN_REL_LAT, KIN_REL_CONT = 0, 1, 2, 3, 4
 CENTER_CELL, CENTER_ORIGIN = 0, 1
 
 OBS_FIELDS = ("energy", "kinetic", "potential", "norm2", "x", "y", "z", "r2", "parity_even")

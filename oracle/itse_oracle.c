@@ -39,7 +39,8 @@ typedef struct {
     double a;
     double mass;
     double dtau;
-    int kin;            /* 1: H_K^(1), 2: H_K^(2), 3: H_K^(3), 4: relativistic with k^2 */
+    int kin;            /* 0: H_K^(0) finite differences, Dirichlet box; 1: H_K^(1), 2: H_K^(2),
+                           3: H_K^(3), 4: relativistic with k^2 */
     int subtract_rest;  /* relativistic forms: 1 -> sqrt(p^2+m^2) - m */
     int center;         /* 0: off-grid cell centre (N-1)/2, 1: lattice origin */
 } orc_lattice;
@@ -229,14 +230,15 @@ static double symbol_value(const orc_lattice *L, double kx, double ky, double kz
 
 static int lattice_ok(const orc_lattice *L)
 {
-    return L && L->n >= 2 && L->a > 0.0 && L->mass > 0.0 && L->kin >= 1 && L->kin <= 4 &&
+    return L && L->n >= 2 && L->a > 0.0 && L->mass > 0.0 && L->kin >= 0 && L->kin <= 4 &&
            (L->center == 0 || L->center == 1);
 }
 
-/* Full FP64 symbol on the N^3 momentum grid, same index layout as the spectrum. */
+/* Full FP64 symbol on the N^3 momentum grid, same index layout as the spectrum
+ * (the transform-based kinds 1..4 only). */
 int orc_kinetic_symbol(const orc_lattice *L, double *T)
 {
-    if (!lattice_ok(L) || !T) return ORC_EINVAL;
+    if (!lattice_ok(L) || L->kin == 0 || !T) return ORC_EINVAL;
     const int n = L->n;
 #pragma omp parallel for schedule(static)
     for (int ix = 0; ix < n; ++ix)
@@ -247,10 +249,41 @@ int orc_kinetic_symbol(const orc_lattice *L, double *T)
     return ORC_OK;
 }
 
-/* K psi = IFFT[ T(k) FFT[psi] ] / N^3 for a real psi (result is real). */
+/* H_K^(0) (paper, equation HK0): the finite-difference kinetic term with Dirichlet
+ * boundaries.  Read with the normalisation of its momentum-space form
+ * (4/A^2) sin^2(k/2) / (2M) per axis, i.e.
+ *   H psi(x) = (1/(2 M A^2)) sum over the six neighbours y of (psi(x) - psi(y)),
+ * where psi vanishes outside the N^3 box (the neighbours beyond a face are zero). */
+static void apply_fdtd(const orc_lattice *L, const double *psi, double *out)
+{
+    const int n = L->n;
+    const double c = 1.0 / (2.0 * L->mass * L->a * L->a);
+#pragma omp parallel for schedule(static)
+    for (int ix = 0; ix < n; ++ix)
+        for (int iy = 0; iy < n; ++iy)
+            for (int iz = 0; iz < n; ++iz) {
+                const size_t s = ((size_t)ix * n + iy) * n + iz;
+                const double p = psi[s];
+                double acc = 0.0;
+                acc += p - (ix > 0 ? psi[s - (size_t)n * n] : 0.0);
+                acc += p - (ix < n - 1 ? psi[s + (size_t)n * n] : 0.0);
+                acc += p - (iy > 0 ? psi[s - n] : 0.0);
+                acc += p - (iy < n - 1 ? psi[s + n] : 0.0);
+                acc += p - (iz > 0 ? psi[s - 1] : 0.0);
+                acc += p - (iz < n - 1 ? psi[s + 1] : 0.0);
+                out[s] = c * acc;
+            }
+}
+
+/* K psi = IFFT[ T(k) FFT[psi] ] / N^3 for a real psi (result is real); H_K^(0)
+ * by its stencil. */
 static int apply_kinetic_with(const orc_lattice *L, const double *T, const double *psi, double *out,
                               cplx *work)
 {
+    if (L->kin == 0) {
+        apply_fdtd(L, psi, out);
+        return ORC_OK;
+    }
     const size_t n3 = (size_t)L->n * L->n * L->n;
     for (size_t s = 0; s < n3; ++s) work[s] = psi[s];
     int st = orc_fft3d(L->n, (double *)work, -1);
@@ -271,7 +304,7 @@ int orc_apply_kinetic(const orc_lattice *L, const double *psi, double *out)
     cplx *work = (cplx *)malloc(sizeof(cplx) * n3);
     int st = ORC_ENOMEM;
     if (T && work) {
-        orc_kinetic_symbol(L, T);
+        if (L->kin != 0) orc_kinetic_symbol(L, T);
         st = apply_kinetic_with(L, T, psi, out, work);
     }
     free(T);
@@ -399,7 +432,7 @@ int orc_observe(const orc_lattice *L, int nstates, const double *psi, const doub
     cplx *work = (cplx *)malloc(sizeof(cplx) * n3);
     int st = ORC_ENOMEM;
     if (T && kpsi && work) {
-        orc_kinetic_symbol(L, T);
+        if (L->kin != 0) orc_kinetic_symbol(L, T);
         st = ORC_OK;
         for (int i = 0; i < nstates && !st; ++i) {
             st = apply_kinetic_with(L, T, psi + i * n3, kpsi, work);
@@ -491,7 +524,7 @@ int orc_step(const orc_lattice *L, int nstates, double *psi, const double *v, in
     cplx *work = (cplx *)malloc(sizeof(cplx) * n3);
     int st = ORC_OK;
     if (!T || !kpsi || !work) st = ORC_ENOMEM;
-    if (!st) orc_kinetic_symbol(L, T);
+    if (!st && L->kin != 0) orc_kinetic_symbol(L, T);
     const double h = 0.5 * L->dtau;
     for (int step = 0; step < nsteps && !st; ++step) {
         for (int i = 0; i < nstates && !st; ++i) {
@@ -542,7 +575,7 @@ int orc_certify(const orc_lattice *L, const double *psi, const double *v, double
     cplx *work = (cplx *)malloc(sizeof(cplx) * n3);
     int st = ORC_ENOMEM;
     if (T && kpsi && lp && d && work) {
-        orc_kinetic_symbol(L, T);
+        if (L->kin != 0) orc_kinetic_symbol(L, T);
         st = apply_kinetic_with(L, T, psi, kpsi, work);
         if (!st) {
             const double h = 0.5 * L->dtau;

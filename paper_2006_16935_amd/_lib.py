@@ -13,7 +13,7 @@ ITSE_OK = 0
 STATUS_NAMES = {0: "ITSE_OK", -1: "ITSE_EINVAL", -2: "ITSE_ENOMEM", -3: "ITSE_EUNSTABLE",
                 -4: "ITSE_ENONFINITE", -5: "ITSE_EDEVICE", -6: "ITSE_ESTATE", -7: "ITSE_ENOTFOUND"}
 
-KIN_NR_CONT, KIN_NR_LAT, KIN_REL_LAT, KIN_REL_CONT = 1, 2, 3, 4
+KIN_FDTD, KIN_NR_CONT, KIN_NR_LAT, KIN_REL_LAT, KIN_REL_CONT = 0, 1, 2, 3, 4
 FP64, FP32 = 0, 1
 CENTER_CELL, CENTER_ORIGIN = 0, 1
 DTYPE_F32, DTYPE_F64 = 1, 2

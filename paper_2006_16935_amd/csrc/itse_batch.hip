@@ -109,11 +109,11 @@ extern "C" itse_status itse_batch_create(int count, itse_lattice *const *lats, v
         delete B;
         return st;
     };
-    // group by (n, precision, variant), keeping input order within a group
-    std::map<std::tuple<int, int, int>, std::vector<itse_lattice *>> by;
-    std::vector<std::tuple<int, int, int>> order;
+    // group by (n, precision, variant, H_K^(0) or not), keeping input order within a group
+    std::map<std::tuple<int, int, int, int>, std::vector<itse_lattice *>> by;
+    std::vector<std::tuple<int, int, int, int>> order;
     for (auto *L : B->lats) {
-        auto key = std::make_tuple(L->d.n, L->d.precision, L->variant);
+        auto key = std::make_tuple(L->d.n, L->d.precision, L->variant, L->d.kin == ITSE_KIN_FDTD ? 1 : 0);
         if (!by.count(key)) order.push_back(key);
         by[key].push_back(L);
     }
@@ -137,6 +137,7 @@ extern "C" itse_status itse_batch_create(int count, itse_lattice *const *lats, v
         g.n = std::get<0>(key);
         g.prec = std::get<1>(key);
         g.variant = std::get<2>(key);
+        g.fdtd = std::get<3>(key) != 0;
         g.jobs = dj;
         g.njobs = (int)jobs.size();
         g.lats = dl;

@@ -109,6 +109,9 @@ struct Launch {
     static hipError_t project_gram(int n, int kmax, const JobRef *lats, int nlats, int force, int which,
                                    hipStream_t s);
     static hipError_t combine(int n, const JobRef *jobs, int njobs, void *const *outs, hipStream_t s);
+    // H_K^(0) lattices: stencil, update and sums in one pass (modes of plane_inv)
+    static hipError_t fdtd(int n, int kmax, int mode, const JobRef *jobs, int njobs, hipStream_t s);
+    static int fdtd_blocks(int n);
     static hipError_t convert_in(const void *src, int src_dtype, void *dst, size_t count, hipStream_t s);
     static hipError_t convert_out(const void *src, void *dst, int dst_dtype, size_t count, hipStream_t s);
 };

@@ -113,7 +113,7 @@ struct PlaneFwdF {
     template <int N, int V>
     hipError_t operator()() {
         using G = Geo<R, N, V>;
-        hipLaunchKernelGGL((k_plane_fwd<R, N, V>), dim3(G::NB_PLANE, njobs), dim3(G::NTP), 0, s, jobs);
+        hipLaunchKernelGGL((k_plane_fwd<R, N, V>), dim3(G::NB_PLANE * njobs), dim3(G::NTP), 0, s, jobs);
         return hipGetLastError();
     }
 };
@@ -156,7 +156,7 @@ struct PlaneInvF {
     template <int N, int V>
     hipError_t operator()() {
         using G = Geo<R, N, V>;
-        hipLaunchKernelGGL((k_plane_inv<R, N, V>), dim3(G::NB_PLANE, njobs), dim3(G::NTP), 0, s, jobs, mode);
+        hipLaunchKernelGGL((k_plane_inv<R, N, V>), dim3(G::NB_PLANE * njobs), dim3(G::NTP), 0, s, jobs, mode);
         return hipGetLastError();
     }
 };
@@ -211,6 +211,40 @@ hipError_t Launch<R>::project_gram(int n, int kmax, const JobRef *lats, int nlat
     else if (kmax <= 4) hipLaunchKernelGGL((k_project_gram<R, 4>), grid, dim3(NT), 0, s, lats, force, which);
     else hipLaunchKernelGGL((k_project_gram<R, MAXK>), grid, dim3(NT), 0, s, lats, force, which);
     return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::fdtd(int n, int kmax, int mode, const JobRef *jobs, int njobs, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    auto go = [&](auto nc) -> hipError_t {
+        constexpr int NN = decltype(nc)::value;
+        const dim3 grid(FdGeo<R, NN>::NB * njobs);
+        if (kmax <= 1) hipLaunchKernelGGL((k_fdtd<R, NN, 1>), grid, dim3(NT), 0, s, jobs, mode);
+        else if (kmax <= 2) hipLaunchKernelGGL((k_fdtd<R, NN, 2>), grid, dim3(NT), 0, s, jobs, mode);
+        else if (kmax <= 4) hipLaunchKernelGGL((k_fdtd<R, NN, 4>), grid, dim3(NT), 0, s, jobs, mode);
+        else hipLaunchKernelGGL((k_fdtd<R, NN, MAXK>), grid, dim3(NT), 0, s, jobs, mode);
+        return hipGetLastError();
+    };
+    switch (n) {
+#define ITSE_CASE(NN) \
+    case NN: return go(std::integral_constant<int, NN>{});
+        ITSE_FOR_EACH_N(ITSE_CASE)
+#undef ITSE_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+int Launch<R>::fdtd_blocks(int n) {
+    switch (n) {
+#define ITSE_CASE(NN) \
+    case NN: return FdGeo<R, NN>::NB;
+        ITSE_FOR_EACH_N(ITSE_CASE)
+#undef ITSE_CASE
+    default:
+        return 0;
+    }
 }
 
 template <typename R>

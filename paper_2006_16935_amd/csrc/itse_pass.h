@@ -60,6 +60,21 @@ __device__ __forceinline__ int xcd_local_index(int b, int nb) {
     return (b & 7) * (full >> 3) + (b >> 3);
 }
 
+// Workgroup order of the plane passes: a flat grid of NB sub-planes x nj jobs in
+// which the jobs of one sub-plane are dispatched 8 workgroups apart, so that they
+// run on the same XCD (the hardware hands workgroup b to XCD b mod 8) at nearly
+// the same time and share the sub-plane's rows of the lower states and of V in
+// that XCD's L2.  Returns the sub-plane and sets the job index.
+__device__ __forceinline__ int plane_block(int b, int nb, int nj, int &job) {
+    if (nb % 8 == 0) {
+        const int q = b >> 3;
+        job = q % nj;
+        return (q / nj) * 8 + (b & 7);
+    }
+    job = b / nb;
+    return b % nb;
+}
+
 // ---------------------------------------------------------------------------
 // Schedules: split factor S (sub-planes per plane), waves per workgroup in the
 // plane passes (NWP) and the column pass (NWC), kz columns per column-pass
@@ -429,7 +444,7 @@ __device__ __forceinline__ void block_store_rows(const C2<R> *src, C2<R> *dst_, 
 }
 
 // ---------------------------------------------------------------------------
-// P1: forward plane pass.  grid.x = x * S + r, grid.y = job.
+// P1: forward plane pass.  Flat grid of (x * S + r, job), see plane_block.
 // ---------------------------------------------------------------------------
 template <typename R, int N, int V>
 __global__ void __launch_bounds__((Geo<R, N, V>::NTP)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPE)))
@@ -438,10 +453,12 @@ k_plane_fwd(const JobRef *__restrict__ jobs) {
     constexpr int S = G::S, M = G::M, H = G::H, HP = G::HP, LSZ = G::LSZ, PPW = G::PPW, CPW = G::CPW;
     __shared__ __attribute__((aligned(16))) C2<R> buf[G::PLANE_ELEMS];
     __shared__ C2<R> tw[N];
-    const JobRef job = jobs[blockIdx.y];
+    int jb;
+    const int spb = plane_block(blockIdx.x, G::NB_PLANE, gridDim.x / G::NB_PLANE, jb);
+    const JobRef job = jobs[jb];
     const LatDev &L = *job.lat;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int x = blockIdx.x / S, r = blockIdx.x % S;
+    const int x = spb / S, r = spb % S;
     const C2<R> *twg = (const C2<R> *)L.tw;
     for (int e = tid; e < N; e += G::NTP) tw[e] = twg[e];
     LatView<R> vw;
@@ -782,7 +799,7 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
 }
 
 // ---------------------------------------------------------------------------
-// P3: inverse plane pass + update.  grid.x = x * S + r, grid.y = job.
+// P3: inverse plane pass + update.  Flat grid of (x * S + r, job), see plane_block.
 // mode INV_UPDATE: u_i <- ((1 - h V) psi - dtau K psi) / (1 + h V)   (= A psi - B dtau K psi)
 // mode INV_EVAL: sums only; INV_KOUT: K psi written to L.kout.
 // ---------------------------------------------------------------------------
@@ -795,11 +812,13 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     __shared__ __attribute__((aligned(16))) C2<R> buf[G::PLANE_ELEMS];
     __shared__ C2<R> tw[N];
     __shared__ double red[NQR * (NTP / 64)];
-    const JobRef job = jobs[blockIdx.y];
+    int jb;
+    const int spb = plane_block(blockIdx.x, G::NB_PLANE, gridDim.x / G::NB_PLANE, jb);
+    const JobRef job = jobs[jb];
     const LatDev &L = *job.lat;
     const int i = job.state;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int x = blockIdx.x / S, r = blockIdx.x % S;
+    const int x = spb / S, r = spb % S;
     const C2<R> *twg = (const C2<R> *)L.tw;
     for (int e = tid; e < N; e += NTP) tw[e] = twg[e];
     block_load_rows<R, M * H, H, G::HS, HP, NTP>((const C2<R> *)L.spec[i] + ((size_t)r * N + x) * M * G::HS,
@@ -927,7 +946,167 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
             }
         }
     }
-    block_sums<NQR, NTP>(acc, L.part_rows + ((size_t)i * L.nb_rows + blockIdx.x) * NQR, red);
+    block_sums<NQR, NTP>(acc, L.part_rows + ((size_t)i * L.nb_rows + spb) * NQR, red);
+}
+
+// ---------------------------------------------------------------------------
+// H_K^(0) step (the paper's equation HK0: finite differences, Dirichlet walls):
+// K psi(x) = (1 / (2 M A^2)) sum over the six neighbours y of (psi(x) - psi(y)),
+// psi vanishing outside the N^3 box, fused with the update and the FP64 sums of
+// P3 (same modes, same partial-sum layout).  One pass over the lattice.
+//
+// Workgroup = a tile of TY full rows (y0 .. y0 + TY) and XS planes (x0 .. x0 + XS)
+// of one job; it marches along x.  Each thread owns one 16-byte vector of VL
+// consecutive z in the tile's plane; its values at x - 1, x, x + 1 stay in
+// registers, the plane x with one halo row on each side goes through LDS for the
+// y and z neighbours.  Every load is issued one plane ahead of its use.
+// ---------------------------------------------------------------------------
+constexpr int fd_rows(int n, int gpr) {
+    int best = 1;
+    for (int t = 1; t <= n; ++t)
+        if (n % t == 0 && t * gpr <= NT) best = t;
+    return best;
+}
+constexpr int fd_segments(int n, int tiles) {
+    int best = 1;
+    for (int sg = 1; sg <= n; ++sg)
+        if (n % sg == 0 && n / sg >= 16 && tiles * sg <= 1024) best = sg;
+    return best;
+}
+
+template <typename R, int N>
+struct FdGeo {
+    static constexpr int VL = VLEN<R>;
+    static constexpr int GPR = N / VL;                      // vectors per row
+    static constexpr int TY = fd_rows(N, GPR);              // rows per tile
+    static constexpr int TILES = N / TY;
+    static constexpr int NSEG = fd_segments(N, TILES);      // x segments
+    static constexpr int XS = N / NSEG;
+    static constexpr int NB = TILES * NSEG;                 // workgroups per state
+    static constexpr int TV = TY * GPR;                     // vectors per plane tile
+    static_assert(N % VL == 0 && TV <= NT, "tile fits the workgroup");
+};
+
+// psi = sum_(j<=i) c_j u_j at one vector (FP64 combination, rounded once); KM
+// bounds the number of states (i < KM).
+template <typename R, int KM>
+__device__ __forceinline__ Vec<R> lazy_vec(const LatView<R> &vw, size_t off, bool ok) {
+    constexpr int VL = VLEN<R>;
+    Vec<R> u[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) u[j] = (j <= vw.i && ok) ? *(const ITSE_GLOBAL Vec<R> *)(vw.u[j] + off) : Vec<R>{};
+    Vec<R> out;
+#pragma unroll
+    for (int k = 0; k < VL; ++k) {
+        double a = 0.0;
+#pragma unroll
+        for (int j = 0; j < KM; ++j)
+            if (j <= vw.i && vw.c[j] != 0.0) a += vw.c[j] * (double)u[j][k];
+        out[k] = ok ? (R)a : (R)0;
+    }
+    return out;
+}
+
+template <typename R, int N, int KM>
+__global__ void __launch_bounds__(NT) k_fdtd(const JobRef *__restrict__ jobs, int mode) {
+    using G = FdGeo<R, N>;
+    constexpr int VL = G::VL, GPR = G::GPR, TY = G::TY, XS = G::XS, TV = G::TV;
+    __shared__ __attribute__((aligned(16))) R pl[(TY + 2) * N];
+    __shared__ double red[NQR * (NT / 64)];
+    // flat grid (tile, segment, job); consecutive tiles share halo rows: same XCD
+    const int nb = G::NB * (int)(gridDim.x / G::NB);
+    const int b = xcd_local_index(blockIdx.x, nb);
+    const int wg = b % G::NB, jb = b / G::NB;
+    const int tile = wg % G::TILES, seg = wg / G::TILES;
+    const int y0 = tile * TY, x0 = seg * XS;
+    const JobRef job = jobs[jb];
+    const LatDev &L = *job.lat;
+    const int i = job.state;
+    LatView<R> vw;
+    load_view(vw, L, i);
+    const ITSE_GLOBAL R *v = gmem((const R *)L.v);
+    ITSE_GLOBAL R *u = gmem((R *)state_buf(L, L.step, 1, i));
+    ITSE_GLOBAL R *kout = gmem((R *)L.kout);
+    const R h = (R)L.h, dt = (R)L.dtau;
+    const R cK = (R)(1.0 / (2.0 * L.mass * L.a * L.a));
+    const bool mom = L.moments != 0;
+    const int center = L.center;
+    const double a = L.a;
+    const int t = threadIdx.x;
+    const bool own = t < TV;
+    const int row = own ? t / GPR : 0, g = own ? t % GPR : 0;
+    const int y = y0 + row, z0 = g * VL;
+    // halo vectors: threads t < 2 GPR load row y0 - 1 (first GPR) or y0 + TY
+    const bool hal = t < 2 * GPR;
+    const int hrow = hal ? t / GPR : 0, hg = hal ? t % GPR : 0;
+    const int hy = hrow == 0 ? y0 - 1 : y0 + TY;
+    const bool hin = hal && hy >= 0 && hy < N;
+    auto off = [&](int xx, int yy, int zz) { return ((size_t)xx * N + yy) * N + zz; };
+    // the planes before the first and after the last are outside the box for
+    // x0 = 0 and x0 + XS = N, else real planes of the lattice
+    Vec<R> pm = lazy_vec<R, KM>(vw, off(x0 > 0 ? x0 - 1 : 0, y, z0), own && x0 > 0);
+    Vec<R> pc = lazy_vec<R, KM>(vw, off(x0, y, z0), own);
+    Vec<R> hc = lazy_vec<R, KM>(vw, off(x0, hin ? hy : 0, hg * VL), hin);
+    Vec<R> vc = own ? *(const ITSE_GLOBAL Vec<R> *)(v + off(x0, y, z0)) : Vec<R>{};
+    double acc[NQR];
+#pragma unroll
+    for (int q = 0; q < NQR; ++q) acc[q] = 0.0;
+    const double cy = site_coord(y, N, center, a);
+#pragma unroll 1
+    for (int xx = x0; xx < x0 + XS; ++xx) {
+        // loads for the next plane
+        const bool nx = xx + 1 < N;
+        const Vec<R> pn = lazy_vec<R, KM>(vw, off(nx ? xx + 1 : 0, y, z0), own && nx);
+        const bool hnext = hin && xx + 1 < x0 + XS;
+        const Vec<R> hn = lazy_vec<R, KM>(vw, off(hnext ? xx + 1 : 0, hin ? hy : 0, hg * VL), hnext);
+        const Vec<R> vn = (own && xx + 1 < x0 + XS) ? *(const ITSE_GLOBAL Vec<R> *)(v + off(xx + 1, y, z0))
+                                                     : Vec<R>{};
+        // plane xx with its halo rows into LDS
+        if (own) *(Vec<R> *)&pl[(row + 1) * N + z0] = pc;
+        if (hal) *(Vec<R> *)&pl[(hrow == 0 ? 0 : TY + 1) * N + hg * VL] = hc;
+        __syncthreads();
+        if (own) {
+            const Vec<R> ym = *(const Vec<R> *)&pl[row * N + z0];
+            const Vec<R> yp = *(const Vec<R> *)&pl[(row + 2) * N + z0];
+            const R zl = z0 > 0 ? pl[(row + 1) * N + z0 - 1] : (R)0;
+            const R zr = z0 + VL < N ? pl[(row + 1) * N + z0 + VL] : (R)0;
+            const double cx = site_coord(xx, N, center, a);
+            Vec<R> un, kv;
+#pragma unroll
+            for (int k = 0; k < VL; ++k) {
+                const R left = k > 0 ? pc[k - 1] : zl;
+                const R right = k + 1 < VL ? pc[k + 1] : zr;
+                const R p_ = pc[k];
+                const R kr = cK * ((R)6 * p_ - pm[k] - pn[k] - ym[k] - yp[k] - left - right);
+                const R vr = vc[k];
+                const R hv = h * vr;
+                const R unv = (p_ * ((R)1 - hv) - dt * kr) / ((R)1 + hv);
+                un[k] = unv;
+                kv[k] = kr;
+                const double pd = (double)p_;
+                acc[RQ_PP] += pd * pd;
+                acc[RQ_PK] += pd * (double)kr;
+                acc[RQ_VPP] += (double)vr * pd * pd;
+                acc[RQ_UU] += (double)unv * (double)unv;
+                if (mom) {
+                    const double cz = site_coord(z0 + k, N, center, a);
+                    const double w2 = pd * pd;
+                    acc[RQ_X] += cx * w2;
+                    acc[RQ_Y] += cy * w2;
+                    acc[RQ_Z] += cz * w2;
+                    acc[RQ_R2] += (cx * cx + cy * cy + cz * cz) * w2;
+                }
+            }
+            if (mode == INV_UPDATE) *(ITSE_GLOBAL Vec<R> *)(u + off(xx, y, z0)) = un;
+            else if (mode == INV_KOUT) *(ITSE_GLOBAL Vec<R> *)(kout + off(xx, y, z0)) = kv;
+        }
+        __syncthreads();
+        pm = pc;
+        pc = pn;
+        hc = hn;
+        vc = vn;
+    }
+    block_sums<NQR, NT>(acc, L.part_rows + ((size_t)i * L.nb_rows + wg) * NQR, red);
 }
 
 // ---------------------------------------------------------------------------

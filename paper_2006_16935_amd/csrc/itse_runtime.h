@@ -26,6 +26,7 @@ struct Group {
     int nlats = 0;
     int kmax = 1;                  // largest number of states among the lattices
     int needs = NEED_PROJECT | NEED_GRAM;  // optional passes a step launches
+    bool fdtd = false;             // H_K^(0): one stencil pass instead of the transforms
 };
 
 itse_status fail(itse_status st, const char *fmt, ...);

@@ -285,6 +285,7 @@ static void kinetic_axis_table(const itse_desc &d, std::vector<double> &tab) {
         const double s = std::sin(0.5 * k);
         switch (d.kin) {
         case ITSE_KIN_NR_CONT: tab[i] = k * k / (2.0 * d.a * d.a * d.mass); break;
+        case ITSE_KIN_FDTD:  // bounded by the periodic stencil's symbol
         case ITSE_KIN_NR_LAT: tab[i] = 4.0 * s * s / (2.0 * d.a * d.a * d.mass); break;
         case ITSE_KIN_REL_LAT: tab[i] = 4.0 * s * s / (d.a * d.a); break;
         default: tab[i] = k * k / (d.a * d.a); break;
@@ -297,7 +298,7 @@ double max_symbol(const itse_desc &d) {
     kinetic_axis_table(d, tab);
     const double mx = *std::max_element(tab.begin(), tab.end());
     const double s = 3.0 * mx;
-    if (d.kin == ITSE_KIN_NR_CONT || d.kin == ITSE_KIN_NR_LAT) return s;
+    if (d.kin == ITSE_KIN_NR_CONT || d.kin == ITSE_KIN_NR_LAT || d.kin == ITSE_KIN_FDTD) return s;
     const double e = std::sqrt(s + d.mass * d.mass);
     return d.subtract_rest_mass ? s / (e + d.mass) : e;
 }
@@ -344,6 +345,7 @@ static itse_status twiddles(int n, int prec, void **out) {
 // ------------------------------------------------------------------------------------
 template <typename R>
 static hipError_t seq_forward_kin(const Group &g, int inv_mode, hipStream_t s) {
+    if (g.fdtd) return Launch<R>::fdtd(g.n, g.kmax, inv_mode, g.jobs, g.njobs, s);
     hipError_t e;
     if ((e = Launch<R>::plane_fwd(g.n, g.variant, g.jobs, g.njobs, s)) != hipSuccess) return e;
     if ((e = Launch<R>::columns(g.n, g.variant, COL_KIN, 1, g.jobs, g.njobs, nullptr, s)) != hipSuccess) return e;
@@ -463,6 +465,7 @@ Group single_group(itse_lattice *L) {
     g.nlats = 1;
     g.kmax = L->d.nstates;
     g.needs = step_needs(L->host, L->d.nstates);
+    g.fdtd = L->d.kin == ITSE_KIN_FDTD;
     return g;
 }
 
@@ -501,7 +504,10 @@ extern "C" size_t itse_footprint_bytes(const itse_desc *d) {
     if (prec_supported(d->n, d->precision)) {
         const int nv = d->precision == ITSE_FP32 ? Launch<float>::variants(d->n) : Launch<double>::variants(d->n);
         for (int v = 0; v < nv; ++v) {
-            const Sched s = prec_schedule(d->n, d->precision, v);
+            Sched s = prec_schedule(d->n, d->precision, v);
+            if (d->kin == ITSE_KIN_FDTD)
+                s.nb_rows = d->precision == ITSE_FP32 ? Launch<float>::fdtd_blocks(d->n)
+                                                      : Launch<double>::fdtd_blocks(d->n);
             const size_t a = (size_t)MAXK * ((size_t)s.nb_rows * NQR + (size_t)s.nb_cols * NQC + s.nb_proj) * 8 +
                              (size_t)s.nb_gram * (MAXK * (MAXK + 1) / 2) * 8;
             arena = std::max(arena, a);
@@ -529,7 +535,7 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
     if (!(d->a > 0) || !(d->mass > 0) || !(d->dtau > 0) || !std::isfinite(d->a) || !std::isfinite(d->mass) ||
         !std::isfinite(d->dtau))
         return fail(ITSE_EINVAL, "a, mass and dtau must be finite and > 0");
-    if (d->kin < 1 || d->kin > 4) return fail(ITSE_EINVAL, "kin = %d", d->kin);
+    if (d->kin < 0 || d->kin > 4) return fail(ITSE_EINVAL, "kin = %d", d->kin);
     if (d->precision != ITSE_FP32 && d->precision != ITSE_FP64) return fail(ITSE_EINVAL, "precision");
     if (d->center != ITSE_CENTER_CELL && d->center != ITSE_CENTER_ORIGIN) return fail(ITSE_EINVAL, "center");
     if (d->nstates < 1 || d->nstates > MAXK) return fail(ITSE_EINVAL, "nstates = %d (1..%d)", d->nstates, MAXK);
@@ -547,6 +553,9 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
     L->alloc_user = alloc_user;
     L->variant = schedule_variant_for(d->n, d->precision);
     L->sched = prec_schedule(d->n, d->precision, L->variant);
+    if (d->kin == ITSE_KIN_FDTD)
+        L->sched.nb_rows = d->precision == ITSE_FP32 ? Launch<float>::fdtd_blocks(d->n)
+                                                     : Launch<double>::fdtd_blocks(d->n);
     const int n = d->n, K = d->nstates;
     const size_t w = real_bytes(d->precision);
     const size_t n3 = (size_t)n * n * n;
@@ -1203,7 +1212,9 @@ static hipError_t launch_pass(const Group &g, int p, hipStream_t s) {
     switch (p) {
     case 0: return Launch<R>::plane_fwd(g.n, g.variant, g.jobs, g.njobs, s);
     case 1: return Launch<R>::columns(g.n, g.variant, COL_KIN, 1, g.jobs, g.njobs, nullptr, s);
-    case 2: return Launch<R>::plane_inv(g.n, g.variant, INV_UPDATE, g.jobs, g.njobs, s);
+    case 2:
+        return g.fdtd ? Launch<R>::fdtd(g.n, g.kmax, INV_UPDATE, g.jobs, g.njobs, s)
+                      : Launch<R>::plane_inv(g.n, g.variant, INV_UPDATE, g.jobs, g.njobs, s);
     case 3: return (g.needs & NEED_PROJECT) ? Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, 1, s) : hipSuccess;
     case 4:
         return (g.needs & NEED_GRAM) ? Launch<R>::project_gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s) : hipSuccess;
@@ -1223,7 +1234,8 @@ extern "C" itse_status itse_profile_step(itse_lattice *L, int nsteps, double *ms
     // passes a step of these options does not launch are reported as 0
     bool launched[NPASS];
     for (int p = 0; p < NPASS; ++p)
-        launched[p] = !((p == 3 && !(g.needs & NEED_PROJECT)) || (p == 4 && !(g.needs & NEED_GRAM)));
+        launched[p] = !((p == 3 && !(g.needs & NEED_PROJECT)) || (p == 4 && !(g.needs & NEED_GRAM)) ||
+                        (p < 2 && g.fdtd));
     std::vector<hipEvent_t> ev((size_t)nsteps * (NPASS + 1));
     for (auto &e : ev) HIPCHK(hipEventCreate(&e));
     for (int s = 0; s < nsteps; ++s) {
@@ -1257,7 +1269,8 @@ extern "C" itse_status itse_profile_step(itse_lattice *L, int nsteps, double *ms
     for (auto &e : ev) (void)hipEventDestroy(e);
     if (names && names_len) {
         std::string js = "[";
-        for (int p = 0; p < NPASS; ++p) js += std::string(p ? ", " : "") + "\"" + pass_names[p] + "\"";
+        for (int p = 0; p < NPASS; ++p)
+            js += std::string(p ? ", " : "") + "\"" + (p == 2 && g.fdtd ? "k_fdtd" : pass_names[p]) + "\"";
         js += "]";
         snprintf(names, names_len, "%s", js.c_str());
     }

@@ -1,0 +1,129 @@
+"""GPU parity of the H_K^(0) path (paper, equation HK0: 7-point finite differences
+with psi = 0 outside the box), one fused stencil + update + sums pass per state,
+through the C ABI, against the FP64 oracle.
+
+Tolerances: FP64 lattices 1e-12 (max-abs / max) for one kinetic application and
+1e-10 relative for energies along trajectories; FP32 lattices 1e-6 of the largest
+value for one application (a few FP32 roundings per site) and 1e-5 relative on
+energies."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def _lat(itse, n, prec, nstates=1, a=0.25, mass=1.2, center="cell"):
+    dtau = a * a * mass / 8
+    return itse.Lattice(n, a, mass, dtau, kin=itse.KIN_FDTD, precision=prec, center=center, nstates=nstates)
+
+
+def _olat(orc, lat):
+    d = lat.desc
+    return orc.lattice(d.n, d.a, d.mass, d.dtau, 0, True, "cell" if d.center == 0 else "origin")
+
+
+@pytest.mark.parametrize("n,prec", [(8, "fp64"), (12, "fp32"), (24, "fp64"), (32, "fp32"), (48, "fp64"),
+                                    (96, "fp32"), (128, "fp64"), (192, "fp32"), (256, "fp32"), (256, "fp64")])
+def test_fdtd_apply_kinetic(itse, orc, n, prec):
+    lat = _lat(itse, n, prec)
+    dt = np.float32 if prec == "fp32" else np.float64
+    psi = synth.random_state(n, 700 + n, dtype=dt)
+    lat.set_state(0, psi)
+    got = lat.apply_kinetic(0).cpu().numpy().astype(np.float64)
+    ref = orc.apply_kinetic(_olat(orc, lat), psi.astype(np.float64))
+    assert _rel(got, ref) < (1e-12 if prec == "fp64" else 1e-6)
+    lat.close()
+
+
+@pytest.mark.parametrize("n,prec,center,parity,axes", [
+    (24, "fp64", "cell", (1, -1, -1), (7, 7, 7)),
+    (32, "fp32", "cell", (1, -1, 0), (7, 4, 7)),
+    (48, "fp64", "origin", (0, 0, 0), (7, 7, 7)),
+])
+def test_fdtd_multistate_steps(itse, orc, n, prec, center, parity, axes):
+    """Three states with projections and Gram-Schmidt every step: energies, norms,
+    moments and final states follow the oracle."""
+    steps = 8
+    a = 0.25
+    lat = _lat(itse, n, prec, nstates=3, a=a, center=center)
+    dt = np.float32 if prec == "fp32" else np.float64
+    v = synth.potential_cornell(n, a, center, sigma=0.2, alpha=0.4).astype(dt)
+    states = synth.random_states(n, 3, seed=80 + n, dtype=dt)
+    lat.set_potential(v)
+    for i, s in enumerate(states):
+        lat.set_state(i, s)
+    lat.set_options(ortho_every=1, moments=True, parity=parity, axes=axes)
+    lat.step(steps)
+    hist = lat.history(steps)
+    ostates, ohist = orc.step(_olat(orc, lat), [s.astype(np.float64) for s in states], v.astype(np.float64),
+                              steps, parity=parity, axes=axes)
+    etol = 1e-10 if prec == "fp64" else 1e-5
+    for s in range(steps):
+        for i in range(3):
+            for f in ("energy", "norm2", "x", "r2"):
+                g, r = hist[s][i][f], ohist[s][i][f]
+                assert abs(g - r) <= etol * max(1.0, abs(r)), (s, i, f, g, r)
+    for i in range(3):
+        assert _rel(lat.get_state(i), ostates[i]) < (1e-10 if prec == "fp64" else 1e-4)
+    lat.close()
+
+
+def test_fdtd_large_first_steps(itse, orc):
+    """256^3 FP32, three states (parity +, -, - and Gram-Schmidt), Cornell potential:
+    the first steps' energies match the FP64 oracle on the same FP32 inputs."""
+    n, a = 256, 0.025
+    lat = _lat(itse, n, "fp32", nstates=3, a=a, mass=1.3, center="origin")
+    v = synth.potential_cornell(n, a, "origin", sigma=0.2, alpha=0.4).astype(np.float32)
+    states = [s.astype(np.float32) for s in synth.random_states(n, 3, seed=3)]
+    lat.set_potential(v)
+    for i, s in enumerate(states):
+        lat.set_state(i, s)
+    lat.set_options(ortho_every=1, parity=(1, -1, -1))
+    lat.step(2)
+    hist = lat.history(2)
+    _, ohist = orc.step(_olat(orc, lat), [s.astype(np.float64) for s in states], v.astype(np.float64), 2,
+                        parity=(1, -1, -1))
+    for s in range(2):
+        for i in range(3):
+            g, r = hist[s][i]["energy"], ohist[s][i]["energy"]
+            assert abs(g - r) <= 1e-5 * abs(r), (s, i, g, r)
+    lat.close()
+
+
+def test_fdtd_in_batch_matches_alone(itse):
+    """H_K^(0) lattices group apart from the transform ones in a batch and give the
+    same results bitwise as alone."""
+    mk = []
+    for n, kin in ((32, 0), (32, 3), (48, 0)):
+        a = 0.25
+        dtau = a * a * 1.2 / 8 if kin == 0 else a / 4
+        lat = itse.Lattice(n, a, 1.2, dtau, kin=kin, precision="fp32", center="cell", nstates=2)
+        lat.set_potential(synth.potential_harmonic(n, a, "cell", 0.5).astype(np.float32))
+        for i, s in enumerate(synth.random_states(n, 2, seed=n + kin, dtype=np.float32)):
+            lat.set_state(i, s)
+        lat.set_options(ortho_every=1)
+        mk.append(lat)
+    alone = []
+    for lat in mk:
+        d = lat.desc
+        b = itse.Lattice(d.n, d.a, d.mass, d.dtau, kin=d.kin, precision="fp32", center="cell", nstates=2)
+        b.set_potential(synth.potential_harmonic(d.n, d.a, "cell", 0.5).astype(np.float32))
+        for i, s in enumerate(synth.random_states(d.n, 2, seed=d.n + d.kin, dtype=np.float32)):
+            b.set_state(i, s)
+        b.set_options(ortho_every=1)
+        b.step(20)
+        alone.append(b)
+    batch = itse.Batch(mk)
+    batch.step(20)
+    for la, lb in zip(mk, alone):
+        for i in range(2):
+            assert np.array_equal(la.get_state(i, np.float32), lb.get_state(i, np.float32))
+    batch.close()
+    for lat in mk + alone:
+        lat.close()

@@ -185,3 +185,59 @@ def test_relativistic_oscillator_worked_example(orc):
     assert abs(e0 - ref) <= g["E0_relative_agreement"] * ref
     # the paper's own tau = 10 value lies above the converged lattice value
     assert e0 < g["E0_minus_M_numeric_tau10"]
+
+
+# ---------------------------------------------------------------------------------
+# H_K^(0) (paper, equation HK0): finite differences with Dirichlet boundaries, the
+# wave-function vanishing outside the N^3 box.
+# ---------------------------------------------------------------------------------
+@pytest.mark.parametrize("n,a,m", [(6, 0.3, 1.0), (12, 0.2, 2.0)])
+def test_hk0_is_dirichlet_laplacian(orc, n, a, m):
+    """Brute force: the dense Kronecker sum of 1D second-difference matrices with no
+    wrap-around (Dirichlet walls), (2 delta_ij - delta_i,j+-1) / (2 M A^2) per axis,
+    applied to a random state."""
+    L = orc.lattice(n, a, m, kin=0)
+    D = (2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)) / (2 * m * a * a)
+    I = np.eye(n)
+    H = np.kron(np.kron(D, I), I) + np.kron(np.kron(I, D), I) + np.kron(np.kron(I, I), D)
+    psi = np.random.default_rng(n).standard_normal((n, n, n))
+    ref = (H @ psi.reshape(-1)).reshape(n, n, n)
+    assert np.abs(orc.apply_kinetic(L, psi) - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("modes", [(1, 1, 1), (2, 1, 3), (5, 4, 1)])
+def test_hk0_sine_modes(orc, modes):
+    """Closed form: products of sin(pi m (x + 1) / (N + 1)) vanish just outside the
+    box and are eigenvectors with eigenvalue sum_l 4 sin^2(pi m_l / (2 (N + 1))) /
+    (2 M A^2), the momentum-space form of the paper with k = pi m / (N + 1)."""
+    n, a, m = 12, 0.25, 1.5
+    L = orc.lattice(n, a, m, kin=0)
+    x = np.arange(n)
+    f = [np.sin(np.pi * q * (x + 1) / (n + 1)) for q in modes]
+    psi = f[0][:, None, None] * f[1][None, :, None] * f[2][None, None, :]
+    lam = sum(4 * np.sin(np.pi * q / (2 * (n + 1))) ** 2 for q in modes) / (2 * m * a * a)
+    assert np.abs(orc.apply_kinetic(L, psi) - lam * psi).max() < 1e-13 * lam
+
+
+def test_hk0_step_fixed_point(orc):
+    """The step map with H_K^(0) keeps the product of 1D ground states of the
+    Dirichlet K + sV (s = (1 + lambda)/2, from dense 1D eigensolves) invariant, as
+    for the periodic kinds."""
+    n, a, m, dtau = 16, 0.3, 1.0, 0.01
+    L = orc.lattice(n, a, m, dtau=dtau, kin=0, center="cell")
+    c = (np.arange(n) - 0.5 * (n - 1)) * a
+    v1 = 0.5 * c * c
+    D = (2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)) / (2 * m * a * a)
+    s = 1.0
+    for _ in range(200):
+        e, U = np.linalg.eigh(D + s * np.diag(v1))
+        lam = 1.0 - dtau * 3 * e[0]
+        s = 0.5 * (1.0 + lam)
+    e, U = np.linalg.eigh(D + s * np.diag(v1))
+    u = U[:, 0]
+    start = u[:, None, None] * u[None, :, None] * u[None, None, :]
+    v = v1[:, None, None] + v1[None, :, None] + v1[None, None, :]
+    out, hist = orc.step(L, [start], v, 50)
+    e_fp = 3 * (u @ D @ u + u @ (v1 * u))
+    assert abs(hist[0][0]["energy"] - e_fp) < 1e-12
+    assert np.abs(out[0] - start).max() < 1e-10
