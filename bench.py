@@ -370,6 +370,32 @@ def main():
         extra["fp64_ms_per_step"] = secs64 * 1000.0 / steps64
         lat64.close()
 
+    # H_K^(0) (finite differences, Dirichlet walls): the same three-state workload
+    # with one fused stencil pass per state instead of the transforms, and the bare
+    # one-state step (12 bytes per site in FP32: psi, V, psi')
+    pf = dataclasses.replace(p, kin=0, dtau=p.a * p.a * p.mass / 8)
+    latf = make_lattice(itse, pf, v32, st32, fp32=True)
+    secsf = timed_steps(torch, latf, args.steps, args.warmup)
+    proff = latf.profile_step(args.profile_steps)
+    latf.close()
+    pf1 = dataclasses.replace(pf, nstates=1, parity=(0,))
+    latf1 = make_lattice(itse, pf1, v32, st32[:1], fp32=True)
+    secsf1 = timed_steps(torch, latf1, args.steps, args.warmup)
+    proff1 = latf1.profile_step(args.profile_steps)
+    latf1.close()
+    fd_bytes = float(n ** 3) * 4 * sum(i + 1 + 2 for i in range(p.nstates))
+    extra["fdtd"] = {
+        "site_steps_per_s": sites * args.steps / secsf,
+        "ms_per_step": secsf * 1000.0 / args.steps,
+        "passes_ms": proff,
+        "k_fdtd_gbs": fd_bytes / (proff["k_fdtd"] * 1e-3) / 1e9,
+        "k_fdtd_frac": fd_bytes / (proff["k_fdtd"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "k1_site_steps_per_s": n ** 3 * args.steps / secsf1,
+        "k1_ms_per_step": secsf1 * 1000.0 / args.steps,
+        "k1_passes_ms": proff1,
+        "k1_hbm_frac": 12.0 * n ** 3 / (secsf1 / args.steps) / 1e9 / HBM_PEAK_GBS,
+    }
+
     out = {
         "metric": "site-steps/s at 256^3 (FP32 steps with FP64 reductions)",
         "value": value,
