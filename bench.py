@@ -53,6 +53,29 @@ def pass_bytes(n: int, w: int, nstates: int, parity, ortho: bool, axes=None):
     }
 
 
+def measured_traffic(kernel: str, variant: int):
+    """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, scaled by a plain
+    copy) from the committed counter summary of the 256^3 FP32 three-state step, if
+    it was taken with this schedule variant from the current kernel sources."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        lines = open(os.path.join(root, "profiles", "step_256_fp32_k3.md")).read().splitlines()
+    except OSError:
+        return None
+    rec = None
+    for ln in lines:
+        if ln.startswith("traffic-json: "):
+            rec = json.loads(ln[len("traffic-json: "):])
+    if not rec or rec.get("kernel") != kernel or rec.get("variant") != variant:
+        return None
+    h = hashlib.sha256()
+    for name in ("itse_pass.h", "itse_fft.h", "itse_launch.h", "itse_internal.h"):
+        with open(os.path.join(root, "paper_2006_16935_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return rec["bytes"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
 def build_workload(n: int, fp32: bool):
     import synth
     p = synth.config_precision(n)
@@ -268,6 +291,8 @@ def main():
     ap.add_argument("--requests", type=int, default=24)
     ap.add_argument("--qps", type=float, default=4.0)
     ap.add_argument("--budget-gb", type=float, default=288.0)
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only step the 256^3 FP32 workload a few times and profile its passes (for rocprofv3)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 256 MiB five times (scale for HBM counters)")
     args = ap.parse_args()
@@ -298,6 +323,17 @@ def main():
         print(json.dumps({"metric": "p50/p99 solve latency, serving form", **res}), flush=True)
         return
     n = args.n
+    if args.kernels_only:
+        # the timed workload's passes alone, for profilers: a few graph steps, then
+        # eager launches of each pass (schedule from --schedule, default 2)
+        itse.set_schedule(n, "fp32", args.schedule if args.schedule >= 0 else 2)
+        p, v32, st32 = build_workload(n, fp32=True)
+        lat = make_lattice(itse, p, v32, st32, fp32=True)
+        lat.step(2)
+        prof = lat.profile_step(args.profile_steps)
+        lat.close()
+        print(json.dumps({"passes_ms": prof}), flush=True)
+        return
     # schedule per (n, precision) picked by the library's autotuner (timed outside the
     # measured region; results are deterministic for a given schedule)
     if args.schedule >= 0:
@@ -415,7 +451,9 @@ def main():
                    "schedule": json.loads(itse.schedule(n, "fp32")), "autotune_fp32": tune32,
                    "autotune_fp64": tune64},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(dom, json.loads(itse.schedule(n, "fp32"))["variant"]),
+                     "kernel": dom,
                      "kernel_ms": dom_ms, "kernel_bytes": pb[dom]},
         "passes_ms": prof,
         "passes_bytes": pb,

@@ -18,7 +18,7 @@ struct NVariants<float, 128> {
 };
 template <>
 struct NVariants<float, 256> {
-    static constexpr int value = 4;
+    static constexpr int value = 5;
 };
 template <>
 struct NVariants<double, 256> {
@@ -55,6 +55,8 @@ static hipError_t dispatch(int n, int variant, F f) {
             if (variant == 2) return f.template operator()<NN, 2>();                   \
         if constexpr (NVariants<R, NN>::value > 3)                                     \
             if (variant == 3) return f.template operator()<NN, 3>();                   \
+        if constexpr (NVariants<R, NN>::value > 4)                                     \
+            if (variant == 4) return f.template operator()<NN, 4>();                   \
         return hipErrorInvalidValue;
         ITSE_FOR_EACH_N(ITSE_CASE)
 #undef ITSE_CASE
@@ -113,7 +115,7 @@ struct PlaneFwdF {
     template <int N, int V>
     hipError_t operator()() {
         using G = Geo<R, N, V>;
-        hipLaunchKernelGGL((k_plane_fwd<R, N, V>), dim3(G::NB_PLANE * njobs), dim3(G::NTP), 0, s, jobs);
+        hipLaunchKernelGGL((k_plane_fwd<R, N, V>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0, s, jobs);
         return hipGetLastError();
     }
 };
@@ -156,7 +158,7 @@ struct PlaneInvF {
     template <int N, int V>
     hipError_t operator()() {
         using G = Geo<R, N, V>;
-        hipLaunchKernelGGL((k_plane_inv<R, N, V>), dim3(G::NB_PLANE * njobs), dim3(G::NTP), 0, s, jobs, mode);
+        hipLaunchKernelGGL((k_plane_inv<R, N, V>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0, s, jobs, mode);
         return hipGetLastError();
     }
 };

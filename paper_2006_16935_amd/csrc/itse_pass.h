@@ -60,19 +60,24 @@ __device__ __forceinline__ int xcd_local_index(int b, int nb) {
     return (b & 7) * (full >> 3) + (b >> 3);
 }
 
-// Workgroup order of the plane passes: a flat grid of NB sub-planes x nj jobs in
-// which the jobs of one sub-plane are dispatched 8 workgroups apart, so that they
-// run on the same XCD (the hardware hands workgroup b to XCD b mod 8) at nearly
-// the same time and share the sub-plane's rows of the lower states and of V in
-// that XCD's L2.  Returns the sub-plane and sets the job index.
-__device__ __forceinline__ int plane_block(int b, int nb, int nj, int &job) {
-    if (nb % 8 == 0) {
-        const int q = b >> 3;
-        job = q % nj;
-        return (q / nj) * 8 + (b & 7);
+// Workgroup order of the plane passes: the jobs of one sub-plane are dispatched
+// 8 workgroups apart, so that they run on the same XCD (the hardware hands
+// workgroup b to XCD b mod 8) at nearly the same time and share the sub-plane's
+// rows of the lower states and of V in that XCD's L2.  With NB % 8 == 0 the grid
+// is (8 nj, NB / 8): x = job * 8 + (sub-plane mod 8), y = sub-plane / 8; else
+// (NB, nj).  Returns the sub-plane and sets the job index (no division).
+template <int NB>
+__device__ __forceinline__ int plane_block(int &job) {
+    if constexpr (NB % 8 == 0) {
+        job = blockIdx.x >> 3;
+        return blockIdx.y * 8 + (blockIdx.x & 7);
     }
-    job = b / nb;
-    return b % nb;
+    job = blockIdx.y;
+    return blockIdx.x;
+}
+template <int NB>
+inline dim3 plane_grid(int njobs) {
+    return NB % 8 == 0 ? dim3(8 * njobs, NB / 8) : dim3(NB, njobs);
 }
 
 // ---------------------------------------------------------------------------
@@ -108,6 +113,7 @@ ITSE_PLAN(float, 256, 0, 4, 8, 16, 16)
 ITSE_PLAN(float, 256, 1, 2, 8, 16, 8)
 ITSE_PLAN(float, 256, 2, 4, 8, 8, 8)
 ITSE_PLAN(float, 256, 3, 4, 8, 4, 4)
+ITSE_PLAN(float, 256, 4, 8, 4, 4, 8)
 // FP64
 ITSE_PLAN(double, 8, 0, 1, 1, 5, 1)
 ITSE_PLAN(double, 12, 0, 1, 1, 7, 1)
@@ -146,10 +152,11 @@ struct Geo {
     static constexpr int LSZ = 2 * HP;
     static constexpr int PLANE_ELEMS = M * HP;
     static constexpr int NTP = 64 * NWP;
-    // plane workgroups that fit one CU's 160 KiB of LDS (at most 2), and the waves
+    // plane workgroups that fit one CU's 160 KiB of LDS (at most 4), and the waves
     // per SIMD they need (caps the registers so that they do fit)
     static constexpr int LDS_PLANE = PLANE_ELEMS * (int)sizeof(C2<R>) + N * (int)sizeof(C2<R>) + 64 * NQR;
-    static constexpr int WG_CU = (163840 / LDS_PLANE) >= 2 ? 2 : 1;
+    static constexpr int WG_FIT = 163840 / LDS_PLANE;
+    static constexpr int WG_CU = WG_FIT >= 4 ? 4 : WG_FIT >= 2 ? WG_FIT : 1;
     static constexpr int WPE = (WG_CU * NWP + 3) / 4 > 1 ? (WG_CU * NWP + 3) / 4 : 1;
     // Column pass
     static constexpr int NCH = (H + W - 1) / W;      // kz chunks
@@ -444,7 +451,7 @@ __device__ __forceinline__ void block_store_rows(const C2<R> *src, C2<R> *dst_, 
 }
 
 // ---------------------------------------------------------------------------
-// P1: forward plane pass.  Flat grid of (x * S + r, job), see plane_block.
+// P1: forward plane pass.  Sub-plane x * S + r and job from plane_block.
 // ---------------------------------------------------------------------------
 template <typename R, int N, int V>
 __global__ void __launch_bounds__((Geo<R, N, V>::NTP)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPE)))
@@ -454,7 +461,7 @@ k_plane_fwd(const JobRef *__restrict__ jobs) {
     __shared__ __attribute__((aligned(16))) C2<R> buf[G::PLANE_ELEMS];
     __shared__ C2<R> tw[N];
     int jb;
-    const int spb = plane_block(blockIdx.x, G::NB_PLANE, gridDim.x / G::NB_PLANE, jb);
+    const int spb = plane_block<G::NB_PLANE>(jb);
     const JobRef job = jobs[jb];
     const LatDev &L = *job.lat;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -799,7 +806,7 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
 }
 
 // ---------------------------------------------------------------------------
-// P3: inverse plane pass + update.  Flat grid of (x * S + r, job), see plane_block.
+// P3: inverse plane pass + update.  Sub-plane x * S + r and job from plane_block.
 // mode INV_UPDATE: u_i <- ((1 - h V) psi - dtau K psi) / (1 + h V)   (= A psi - B dtau K psi)
 // mode INV_EVAL: sums only; INV_KOUT: K psi written to L.kout.
 // ---------------------------------------------------------------------------
@@ -813,7 +820,7 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     __shared__ C2<R> tw[N];
     __shared__ double red[NQR * (NTP / 64)];
     int jb;
-    const int spb = plane_block(blockIdx.x, G::NB_PLANE, gridDim.x / G::NB_PLANE, jb);
+    const int spb = plane_block<G::NB_PLANE>(jb);
     const JobRef job = jobs[jb];
     const LatDev &L = *job.lat;
     const int i = job.state;

@@ -18,6 +18,7 @@ pytestmark = pytest.mark.gpu
 
 CASES = [(48, "fp64", 0), (96, "fp64", 0), (128, "fp32", 0), (128, "fp32", 1), (128, "fp64", 0),
          (192, "fp32", 0), (192, "fp64", 0), (256, "fp32", 0), (256, "fp32", 1), (256, "fp32", 2), (256, "fp32", 3),
+         (256, "fp32", 4),
          (256, "fp64", 0), (256, "fp64", 1)]
 
 
