@@ -188,6 +188,8 @@ def serving_run(torch, itse, count: int, qps: float, budget: int, seed: int = 1)
         for r in server.poll():
             done[r["id"]] = (_time.perf_counter() - t0, r)
             site_steps += ids[r["id"]].n ** 3 * ids[r["id"]].nstates * r["steps"]
+            print(f"serving: {len(done)}/{count} done at {done[r['id']][0]:.1f} s, live {live}, queued {queued}",
+                  file=sys.stderr, flush=True)
         if live == 0 and queued == 0 and nxt < count:
             _time.sleep(max(0.0, reqs[nxt][0] - (_time.perf_counter() - t0)))
     wall = _time.perf_counter() - t0
