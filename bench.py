@@ -398,6 +398,17 @@ def main():
     extract_ms = (time.perf_counter() - t0) * 1000.0
     extra["snapshot_overlap"] = {"push_ms": push_ms, "extract_ms": extract_ms,
                                  "estimates": len(snap_obs)}
+    # analysis of the state: box observables and parity weights, radial momentum space
+    lat1.analyse(0, 0.3)
+    t0 = time.perf_counter()
+    ana = lat1.analyse(0, 0.3)
+    analyse_ms = (time.perf_counter() - t0) * 1000.0
+    lat1.momentum_radial(0, 128)
+    t0 = time.perf_counter()
+    lat1.momentum_radial(0, 128)
+    momentum_ms = (time.perf_counter() - t0) * 1000.0
+    extra["analysis"] = {"analyse_ms": analyse_ms, "momentum_radial_ms": momentum_ms,
+                         "rho_box": ana["rho_box"], "w_plus": ana["w_plus"]}
     lat1.close()
     if not args.no_fp64:
         p64, v64, st64 = build_workload(n, fp32=False)

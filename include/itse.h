@@ -193,6 +193,34 @@ itse_status itse_spectrum(itse_lattice *lat, int i, void *out_device);
  * Synchronises. */
 itse_status itse_polish(itse_lattice *lat, int i, itse_obs *out);
 
+/* ---- Analysis of a state -------------------------------------------------
+ * Box normalisation and average radius (section "Finite volume normalization")
+ * and parity weights (section "Parity projection") in the effective volume: the
+ * sites whose coordinates about the potential centre all satisfy
+ * |c_l| <= (1 - min_sep_edge) N A / 2 (a box of side (1 - min_sep_edge) A N). */
+typedef struct {
+    double box_norm2;        /* sum over the box of psi^2 (psi as held: unit norm on the lattice) */
+    double rho_box;          /* <rho> in the box after box normalisation, lattice units */
+    double w_plus, w_minus;  /* box weights of P+ and P- (full inversion)              */
+    double w_minus_axis[3];  /* box weights of P-_{e_k} = (1 + R_perp)(1 - R_k)/4       */
+} itse_analysis;
+
+/* Analysis of state i, 0 <= min_sep_edge < 1.  FP64 sums in a fixed order.  The
+ * first call allocates a few KiB of partial sums through the lattice's allocator.
+ * Synchronises.  Errors: ITSE_EINVAL, ITSE_ENONFINITE if the box holds no weight. */
+itse_status itse_analyse(itse_lattice *lat, int i, double min_sep_edge, itse_analysis *out);
+
+/* Radial momentum-space wave-function of state i: Psi(p) = FFT[psi] scaled so that
+ * (2 pi / (N A))^3 sum_p |Psi(p)|^2 = 1, p on the eigenmode set; momenta grouped in
+ * bins of width 2 pi / (N A) (bin b: |p| in [(b - 1/2), (b + 1/2)) 2 pi / (N A)),
+ * b < nbins <= 512.  Per bin: count[b] momenta, their mean |p| in p[b], the mean
+ * |Psi(p)| in psi[b] and y[b] = sqrt(4 pi) p[b] psi[b] (0 for empty bins).  Any of
+ * the output arrays may be NULL.  The first call allocates a half spectrum and the
+ * partial histograms through the lattice's allocator.  Histogram sums use LDS
+ * atomics (their order within a workgroup is the hardware's).  Synchronises. */
+itse_status itse_momentum_radial(itse_lattice *lat, int i, int nbins, double *count, double *p, double *psi,
+                                 double *y);
+
 /* ---- Snapshot-overlap extraction of excited states ----------------------
  * The paper's procedure (section "The iterative procedure"): while state 0
  * evolves, snapshots of it are kept; the latest wave-function estimates the

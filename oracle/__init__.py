@@ -209,3 +209,82 @@ def certify(L: Lattice, psi: np.ndarray, v: np.ndarray):
     _check(lib().orc_certify(ctypes.byref(L), _dptr(psi), _dptr(v), ctypes.byref(lam),
                              ctypes.byref(res), ctypes.byref(en)), "certify")
     return {"lambda": lam.value, "resid": res.value, "energy": en.value}
+
+
+# ---------------------------------------------------------------------------------
+# Analysis of a state (plain numpy): box normalisation, average radius, parity
+# weights, and the radial momentum-space wave-function.
+# ---------------------------------------------------------------------------------
+def _axis_coord(L: Lattice) -> np.ndarray:
+    idx = np.arange(L.n, dtype=np.float64)
+    if L.center == 0:
+        return (idx - 0.5 * (L.n - 1)) * L.a
+    return np.where(2 * idx <= L.n, idx, idx - L.n) * L.a
+
+
+def _reflect(L: Lattice, psi: np.ndarray, axes: int) -> np.ndarray:
+    idx = np.arange(L.n)
+    m = (L.n - 1 - idx) if L.center == 0 else (-idx) % L.n
+    out = psi
+    if axes & 1:
+        out = out[m, :, :]
+    if axes & 2:
+        out = out[:, m, :]
+    if axes & 4:
+        out = out[:, :, m]
+    return out
+
+
+def analyse(L: Lattice, psi: np.ndarray, min_sep_edge: float) -> dict:
+    """Box-normalised observables of one state (section "Finite volume
+    normalization") and parity weights (section "Parity projection").
+
+    The effective volume keeps the sites whose coordinates about the centre all
+    satisfy |c_l| <= (1 - min_sep_edge) N A / 2, i.e. a box of side
+    (1 - min_sep_edge) A N.  box_norm2 = sum over it of psi^2 (psi as given);
+    rho_box = sum of rho psi^2 / box_norm2 with rho = |r| / A; the weights are
+    sum over the box of (P psi)^2 / box_norm2 for P+ and P- (full inversion) and for
+    P-_{e_k} = (1 + R_perp)(1 - R_k) / 4 (R_k reflects axis k, R_perp the other two
+    axes; the paper prints the prefactor 1/2, which is not idempotent -- read as
+    the projector, whose weight is 1 for a p-wave with m = 0 along e_k)."""
+    psi = np.asarray(psi, dtype=np.float64)
+    c = _axis_coord(L)
+    half = (1.0 - min_sep_edge) * L.n * L.a / 2.0
+    ins = np.abs(c) <= half * (1.0 + 1e-12)
+    box = ins[:, None, None] & ins[None, :, None] & ins[None, None, :]
+    rho = np.sqrt(c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2) / L.a
+    p2 = psi * psi
+    norm = p2[box].sum()
+    r7 = _reflect(L, psi, 7)
+    out = {"box_norm2": norm, "rho_box": (rho * p2)[box].sum() / norm,
+           "w_plus": (0.25 * (psi + r7) ** 2)[box].sum() / norm,
+           "w_minus": (0.25 * (psi - r7) ** 2)[box].sum() / norm}
+    for k, (ax, perp) in enumerate(((1, 6), (2, 5), (4, 3))):
+        pk = 0.25 * (psi + _reflect(L, psi, perp) - _reflect(L, psi, ax) - r7)
+        out[f"w_minus_e{k + 1}"] = (pk * pk)[box].sum() / norm
+    return out
+
+
+def momentum_radial(L: Lattice, psi: np.ndarray, nbins: int) -> dict:
+    """Radial momentum-space wave-function (the comparison with a radial ODE
+    solution near the end of the paper): Psi(p) = FFT[psi] scaled so that
+    (2 pi / (N A))^3 sum_p |Psi(p)|^2 = 1, p_l = 2 pi m_l / (N A) on the eigenmode
+    set, y(p) = sqrt(4 pi) p |Psi(p)|.  Momenta are grouped in bins of width
+    dp = 2 pi / (N A) (bin b holds |p| in [(b - 1/2) dp, (b + 1/2) dp)); per bin:
+    number of momenta, mean |p|, mean |Psi(p)| and y = sqrt(4 pi) p_mean mean|Psi|."""
+    n, a = L.n, L.a
+    F = fft3d(np.asarray(psi, dtype=np.float64), -1)
+    dp = 2.0 * np.pi / (n * a)
+    F = F / np.sqrt(dp ** 3 * (np.abs(F) ** 2).sum())
+    idx = np.arange(n)
+    m = np.where(2 * idx <= n, idx, idx - n) * dp
+    pm = np.sqrt(m[:, None, None] ** 2 + m[None, :, None] ** 2 + m[None, None, :] ** 2)
+    b = np.floor(pm / dp + 0.5).astype(int)
+    keep = b < nbins
+    cnt = np.bincount(b[keep], minlength=nbins).astype(np.float64)
+    ps = np.bincount(b[keep], weights=pm[keep], minlength=nbins)
+    fs = np.bincount(b[keep], weights=np.abs(F)[keep], minlength=nbins)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        pmean = np.where(cnt > 0, ps / cnt, 0.0)
+        fmean = np.where(cnt > 0, fs / cnt, 0.0)
+    return {"count": cnt, "p": pmean, "psi": fmean, "y": np.sqrt(4 * np.pi) * pmean * fmean}

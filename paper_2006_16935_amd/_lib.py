@@ -35,6 +35,17 @@ class Desc(ctypes.Structure):
 OBS_FIELDS = ("energy", "kinetic", "potential", "norm2", "x", "y", "z", "r2", "parity_even")
 
 
+class Analysis(ctypes.Structure):
+    _fields_ = [("box_norm2", ctypes.c_double), ("rho_box", ctypes.c_double), ("w_plus", ctypes.c_double),
+                ("w_minus", ctypes.c_double), ("w_minus_axis", ctypes.c_double * 3)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f in ("box_norm2", "rho_box", "w_plus", "w_minus")}
+        for k in range(3):
+            d[f"w_minus_e{k + 1}"] = self.w_minus_axis[k]
+        return d
+
+
 class Obs(ctypes.Structure):
     _fields_ = [("step", ctypes.c_longlong)] + [(f, ctypes.c_double) for f in OBS_FIELDS]
 
@@ -106,6 +117,8 @@ def load():
         "itse_spectrum": ([vp, ip, vp], ip),
         "itse_polish": ([vp, ip, P(Obs)], ip),
         "itse_sync": ([vp], ip),
+        "itse_analyse": ([vp, ip, ctypes.c_double, P(Analysis)], ip),
+        "itse_momentum_radial": ([vp, ip, ip, P(dp), P(dp), P(dp), P(dp)], ip),
         "itse_snapshot_push": ([vp], ip),
         "itse_snapshot_count": ([vp, P(ip)], ip),
         "itse_snapshot_clear": ([vp], ip),

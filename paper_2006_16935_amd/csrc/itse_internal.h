@@ -112,6 +112,12 @@ struct Launch {
     // H_K^(0) lattices: stencil, update and sums in one pass (modes of plane_inv)
     static hipError_t fdtd(int n, int kmax, int mode, const JobRef *jobs, int njobs, hipStream_t s);
     static int fdtd_blocks(int n);
+    // analysis of one job's state: parts holds analyse_parts(n) doubles, out NAQ
+    static hipError_t analyse(int n, const JobRef *job, double half, double *parts, double *out, hipStream_t s);
+    static size_t analyse_parts(int n);
+    // radial binning of a standard-layout half spectrum: parts holds
+    // n * (3 nbins + 1) doubles, out 3 nbins + 1
+    static hipError_t momentum_bins(int n, const void *spec, int nbins, double *parts, double *out, hipStream_t s);
     static hipError_t convert_in(const void *src, int src_dtype, void *dst, size_t count, hipStream_t s);
     static hipError_t convert_out(const void *src, void *dst, int dst_dtype, size_t count, hipStream_t s);
 };

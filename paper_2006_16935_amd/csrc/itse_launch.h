@@ -250,6 +250,31 @@ int Launch<R>::fdtd_blocks(int n) {
 }
 
 template <typename R>
+size_t Launch<R>::analyse_parts(int n) {
+    return (size_t)n * ANA_CHUNKS * NAQ;
+}
+
+template <typename R>
+hipError_t Launch<R>::analyse(int n, const JobRef *job, double half, double *parts, double *out, hipStream_t s) {
+    hipLaunchKernelGGL((k_analyse<R>), dim3(n * ANA_CHUNKS), dim3(NT), 0, s, job, half, parts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sum_records<R>), dim3(1), dim3(NT), 0, s, (const double *)parts, n * ANA_CHUNKS, (int)NAQ,
+                       out);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t Launch<R>::momentum_bins(int n, const void *spec, int nbins, double *parts, double *out, hipStream_t s) {
+    if (nbins < 1 || nbins > MOM_MAXBINS) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_momentum_bins<R>), dim3(n), dim3(NT), 0, s, (const C2<R> *)spec, n, nbins, parts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sum_records<R>), dim3(1), dim3(NT), 0, s, (const double *)parts, n, 3 * nbins + 1, out);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t Launch<R>::combine(int n, const JobRef *jobs, int njobs, void *const *outs, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_combine<R>), dim3(flat_blocks(n), njobs), dim3(NT), 0, s, jobs, outs);

@@ -1449,6 +1449,115 @@ __global__ void __launch_bounds__(NT) k_combine(const JobRef *__restrict__ jobs,
         out[s] = lazy_psi(vw, s);
 }
 
+// ---------------------------------------------------------------------------
+// Analysis of state psi_i (one job): box normalisation, average radius and parity
+// weights in the effective volume |c_l| <= half (sections "Finite volume
+// normalization" and "Parity projection").  Workgroup (plane x, chunk of rows);
+// per site of the box: psi at the site and at its seven reflections (R1, R2, R4
+// reflect x, y, z; combinations by bits), FP64 partial sums in the order
+// NA_NORM .. NA_PE3.
+// ---------------------------------------------------------------------------
+enum AnaQ { NA_NORM = 0, NA_RHO, NA_PPLUS, NA_PMINUS, NA_PE1, NA_PE2, NA_PE3, NAQ };
+constexpr int ANA_CHUNKS = 8;
+
+template <typename R>
+__global__ void __launch_bounds__(NT) k_analyse(const JobRef *__restrict__ job_, double half, double *parts) {
+    __shared__ double red[NAQ * (NT / 64)];
+    const JobRef job = *job_;
+    const LatDev &L = *job.lat;
+    LatView<R> vw;
+    load_view(vw, L, job.state);
+    const int n = L.n, center = L.center;
+    const double a = L.a;
+    const int x = blockIdx.x / ANA_CHUNKS, ch = blockIdx.x % ANA_CHUNKS;
+    const int rpc = (n + ANA_CHUNKS - 1) / ANA_CHUNKS;
+    const int y0 = ch * rpc, y1 = y0 + rpc < n ? y0 + rpc : n;
+    const double lim = half * (1.0 + 1e-12);
+    double acc[NAQ];
+#pragma unroll
+    for (int q = 0; q < NAQ; ++q) acc[q] = 0.0;
+    const double cx = site_coord(x, n, center, a);
+    if (fabs(cx) <= lim) {
+        const int mx = mirror_idx(x, n, center);
+        for (int e = threadIdx.x; e < (y1 - y0) * n; e += NT) {
+            const int y = y0 + e / n, z = e % n;
+            const double cy = site_coord(y, n, center, a), cz = site_coord(z, n, center, a);
+            if (fabs(cy) > lim || fabs(cz) > lim) continue;
+            const int my = mirror_idx(y, n, center), mz = mirror_idx(z, n, center);
+            auto at = [&](int xx, int yy, int zz) {
+                return (double)lazy_psi(vw, ((size_t)xx * n + yy) * n + zz);
+            };
+            const double v0 = at(x, y, z), v1 = at(mx, y, z), v2 = at(x, my, z), v3 = at(mx, my, z);
+            const double v4 = at(x, y, mz), v5 = at(mx, y, mz), v6 = at(x, my, mz), v7 = at(mx, my, mz);
+            const double rho = sqrt(cx * cx + cy * cy + cz * cz) / a;
+            const double pp = 0.5 * (v0 + v7), pm = 0.5 * (v0 - v7);
+            const double e1 = 0.25 * (v0 + v6 - v1 - v7), e2 = 0.25 * (v0 + v5 - v2 - v7);
+            const double e3 = 0.25 * (v0 + v3 - v4 - v7);
+            acc[NA_NORM] += v0 * v0;
+            acc[NA_RHO] += rho * v0 * v0;
+            acc[NA_PPLUS] += pp * pp;
+            acc[NA_PMINUS] += pm * pm;
+            acc[NA_PE1] += e1 * e1;
+            acc[NA_PE2] += e2 * e2;
+            acc[NA_PE3] += e3 * e3;
+        }
+    }
+    block_sums<NAQ, NT>(acc, parts + (size_t)blockIdx.x * NAQ, red);
+}
+
+// Radial binning of a half spectrum in the standard layout [kx][ky][kz] (kz <= N/2)
+// for the momentum-space wave-function: bin b = round(|m|) of the integer momentum
+// m on the eigenmode set; per bin the number of momenta, the sum of |m| and of
+// |F(m)| over the full spectrum (interior kz count twice: F(-m) = conj F(m)), and
+// the total sum of |F|^2.  One workgroup per kx; LDS histograms (FP64 atomics),
+// then per-workgroup partials [nbins][3] + 1.
+// ---------------------------------------------------------------------------
+constexpr int MOM_MAXBINS = 512;
+
+template <typename R>
+__global__ void __launch_bounds__(NT) k_momentum_bins(const C2<R> *__restrict__ spec, int n, int nbins,
+                                                      double *parts) {
+    __shared__ double hist[3 * MOM_MAXBINS];
+    __shared__ double red[NT / 64];
+    const int h = n / 2 + 1, kx = blockIdx.x;
+    for (int b = threadIdx.x; b < 3 * nbins; b += NT) hist[b] = 0.0;
+    __syncthreads();
+    const int mx = 2 * kx <= n ? kx : kx - n;
+    double f2[1] = {0.0};
+    for (int e = threadIdx.x; e < n * h; e += NT) {
+        const int ky = e / h, kz = e % h;
+        const int my = 2 * ky <= n ? ky : ky - n;
+        const double w = (kz == 0 || 2 * kz == n) ? 1.0 : 2.0;
+        const double mag2 = (double)(mx * mx + my * my + kz * kz);
+        const C2<R> f = spec[((size_t)kx * n + ky) * h + kz];
+        const double af2 = (double)f.x * (double)f.x + (double)f.y * (double)f.y;
+        f2[0] += w * af2;
+        const double mag = sqrt(mag2);
+        const int b = (int)floor(mag + 0.5);
+        if (b < nbins) {
+            atomicAdd(&hist[3 * b], w);
+            atomicAdd(&hist[3 * b + 1], w * mag);
+            atomicAdd(&hist[3 * b + 2], w * sqrt(af2));
+        }
+    }
+    __syncthreads();
+    double *out = parts + (size_t)kx * (3 * nbins + 1);
+    for (int b = threadIdx.x; b < 3 * nbins; b += NT) out[b] = hist[b];
+    block_sums<1, NT>(f2, out + 3 * nbins, red);
+}
+
+// Fixed-order sums of `count` partial records of `width` doubles (one workgroup;
+// R only makes one instance per precision's translation unit).
+template <typename R>
+__global__ void __launch_bounds__(NT) k_sum_records(const double *__restrict__ parts, int count, int width,
+                                                    double *out) {
+    for (int q = threadIdx.x; q < width; q += NT) {
+        double s = 0.0;
+        for (int b = 0; b < count; ++b) s += parts[(size_t)b * width + q];
+        out[q] = s;
+    }
+}
+
 template <typename S, typename D>
 __global__ void __launch_bounds__(NT) k_convert(const S *__restrict__ src, D *__restrict__ dst, size_t count) {
     const size_t stride = (size_t)gridDim.x * NT;

@@ -72,6 +72,9 @@ struct itse_lattice {
     void **snap_ptr_dev = nullptr;     // [ITSE_SNAPSHOTS] device copies of snap[]
     int snap_count = 0, snap_newest = -1;
     itse_lattice *snapx = nullptr;     // estimates of the snapshot-overlap extraction
+    double *ana = nullptr;             // analysis partial sums (device)
+    size_t ana_bytes = 0;
+    void *mom_spec = nullptr;          // half spectrum for the momentum-space analysis
     void *cur_raw(int i) const { return itse::state_buf(host, steps_host, 0, i); }
     void *stage_buf(size_t bytes);
     ~itse_lattice();

@@ -1115,6 +1115,84 @@ extern "C" itse_status itse_polish(itse_lattice *L, int i, itse_obs *out) {
 }
 
 // ------------------------------------------------------------------------------------
+// Analysis of a state (box normalisation, radius, parity weights; momentum space)
+// ------------------------------------------------------------------------------------
+static double *ana_scratch(itse_lattice *L, size_t doubles) {
+    const size_t bytes = doubles * sizeof(double);
+    if (L->ana && L->ana_bytes >= bytes) return L->ana;
+    L->ana = (double *)lat_alloc(L, bytes);
+    L->ana_bytes = L->ana ? bytes : 0;
+    return L->ana;
+}
+
+extern "C" itse_status itse_analyse(itse_lattice *L, int i, double min_sep_edge, itse_analysis *out) {
+    if (!L || !out) return fail(ITSE_EINVAL, "null argument");
+    if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
+    if (!(min_sep_edge >= 0.0 && min_sep_edge < 1.0)) return fail(ITSE_EINVAL, "min_sep_edge = %g", min_sep_edge);
+    const int n = L->d.n;
+    const size_t np = L->d.precision == ITSE_FP32 ? Launch<float>::analyse_parts(n) : Launch<double>::analyse_parts(n);
+    double *buf = ana_scratch(L, np + NAQ);
+    if (!buf) return fail(ITSE_ENOMEM, "analysis sums");
+    const double half = (1.0 - min_sep_edge) * n * L->d.a / 2.0;
+    hipError_t e = L->d.precision == ITSE_FP32
+                       ? Launch<float>::analyse(n, L->jobs_dev + i, half, buf, buf + np, L->stream)
+                       : Launch<double>::analyse(n, L->jobs_dev + i, half, buf, buf + np, L->stream);
+    if (e != hipSuccess) return fail(ITSE_EDEVICE, "analyse: %s", hipGetErrorString(e));
+    double q[NAQ];
+    HIPCHK(hipMemcpyAsync(q, buf + np, sizeof q, hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    if (!(q[NA_NORM] > 0.0) || !std::isfinite(q[NA_NORM])) return fail(ITSE_ENONFINITE, "no weight in the box");
+    out->box_norm2 = q[NA_NORM];
+    out->rho_box = q[NA_RHO] / q[NA_NORM];
+    out->w_plus = q[NA_PPLUS] / q[NA_NORM];
+    out->w_minus = q[NA_PMINUS] / q[NA_NORM];
+    out->w_minus_axis[0] = q[NA_PE1] / q[NA_NORM];
+    out->w_minus_axis[1] = q[NA_PE2] / q[NA_NORM];
+    out->w_minus_axis[2] = q[NA_PE3] / q[NA_NORM];
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_momentum_radial(itse_lattice *L, int i, int nbins, double *count, double *p, double *psi,
+                                            double *y) {
+    if (!L) return fail(ITSE_EINVAL, "null lattice");
+    if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
+    if (nbins < 1 || nbins > MOM_MAXBINS) return fail(ITSE_EINVAL, "nbins = %d (1..%d)", nbins, MOM_MAXBINS);
+    const int n = L->d.n;
+    if (!L->mom_spec) {
+        const size_t h = (size_t)n / 2 + 1;
+        L->mom_spec = lat_alloc(L, (size_t)n * n * h * 2 * real_bytes(L->d.precision));
+        if (!L->mom_spec) return fail(ITSE_ENOMEM, "momentum-space spectrum");
+    }
+    itse_status st = itse_spectrum(L, i, L->mom_spec);
+    if (st) return st;
+    const size_t w = 3 * (size_t)nbins + 1, np = (size_t)n * w;
+    double *buf = ana_scratch(L, np + w);
+    if (!buf) return fail(ITSE_ENOMEM, "momentum histograms");
+    hipError_t e = L->d.precision == ITSE_FP32
+                       ? Launch<float>::momentum_bins(n, L->mom_spec, nbins, buf, buf + np, L->stream)
+                       : Launch<double>::momentum_bins(n, L->mom_spec, nbins, buf, buf + np, L->stream);
+    if (e != hipSuccess) return fail(ITSE_EDEVICE, "momentum bins: %s", hipGetErrorString(e));
+    std::vector<double> q(w);
+    HIPCHK(hipMemcpyAsync(q.data(), buf + np, w * sizeof(double), hipMemcpyDeviceToHost, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));
+    const double pi = 3.14159265358979323846;
+    const double dp = 2.0 * pi / (n * L->d.a);
+    const double total = q[3 * nbins];
+    if (!(total > 0.0) || !std::isfinite(total)) return fail(ITSE_ENONFINITE, "zero or non-finite spectrum");
+    const double scale = 1.0 / std::sqrt(dp * dp * dp * total);
+    for (int b = 0; b < nbins; ++b) {
+        const double c = q[3 * b];
+        const double pm = c > 0.0 ? q[3 * b + 1] / c * dp : 0.0;
+        const double fm = c > 0.0 ? q[3 * b + 2] / c * scale : 0.0;
+        if (count) count[b] = c;
+        if (p) p[b] = pm;
+        if (psi) psi[b] = fm;
+        if (y) y[b] = std::sqrt(4.0 * pi) * pm * fm;
+    }
+    return ITSE_OK;
+}
+
+// ------------------------------------------------------------------------------------
 // Snapshot-overlap extraction of excited states (section "The iterative procedure")
 // ------------------------------------------------------------------------------------
 extern "C" itse_status itse_snapshot_push(itse_lattice *L) {

@@ -231,6 +231,23 @@ class Lattice:
     def sync(self):
         check(self._L.itse_sync(self.h))
 
+    # -- analysis (itse_analyse, itse_momentum_radial) ---------------------------------
+    def analyse(self, i: int, min_sep_edge: float = 0.3) -> dict:
+        """Box normalisation, average radius (lattice units) and parity weights of
+        state i in the effective volume of side (1 - min_sep_edge) A N."""
+        out = _lib.Analysis()
+        check(self._L.itse_analyse(self.h, int(i), float(min_sep_edge), ctypes.byref(out)))
+        return out.as_dict()
+
+    def momentum_radial(self, i: int, nbins: int) -> dict:
+        """Radial momentum-space wave-function of state i in bins of 2 pi / (N A):
+        arrays count, p, psi (mean |Psi(p)|) and y = sqrt(4 pi) p psi."""
+        arrs = {k: np.zeros(int(nbins)) for k in ("count", "p", "psi", "y")}
+        ptr = {k: v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for k, v in arrs.items()}
+        check(self._L.itse_momentum_radial(self.h, int(i), int(nbins), ptr["count"], ptr["p"], ptr["psi"],
+                                           ptr["y"]))
+        return arrs
+
     # -- snapshot-overlap extraction (itse_snapshot_*) ---------------------------------
     def snapshot(self):
         """Keep the current state 0 as the newest snapshot (the ring holds two)."""

@@ -1,0 +1,73 @@
+"""GPU parity of the state analysis through the C ABI against the oracle on the same
+state (read back from the lattice): box normalisation, average radius and parity
+weights (sections "Finite volume normalization" and "Parity projection"), and the
+radial momentum-space wave-function.
+
+Tolerances: the analysis sums are FP64 over the same stored values, 1e-12 relative
+(order of summation); the momentum-space values come from the lattice's own
+transform, 1e-12 relative for FP64 lattices and 1e-5 for FP32 lattices (one FP32
+transform)."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _olat(orc, lat):
+    d = lat.desc
+    return orc.lattice(d.n, d.a, d.mass, d.dtau, d.kin, bool(d.subtract_rest_mass),
+                       "cell" if d.center == 0 else "origin")
+
+
+@pytest.mark.parametrize("n,prec,center,m", [(16, "fp64", "cell", 0.3), (24, "fp32", "origin", 0.3),
+                                             (48, "fp64", "origin", 0.0), (64, "fp32", "cell", 0.5),
+                                             (256, "fp32", "origin", 0.3)])
+def test_analysis_matches_oracle(itse, orc, n, prec, center, m):
+    a = 6.4 / n
+    lat = itse.Lattice(n, a, 1.3, a / 4, kin=3, precision=prec, center=center, nstates=2)
+    dt = np.float32 if prec == "fp32" else np.float64
+    x = synth.axis_coords(n, a, center)
+    g = np.exp(-(x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2) / 1.5)
+    mix = (g * (0.7 + 0.5 * x[None, None, :] + 0.2 * x[:, None, None] * x[None, :, None]))
+    lat.set_state(0, synth.random_state(n, 4, dtype=dt))
+    lat.set_state(1, mix.astype(dt))
+    for i in range(2):
+        got = lat.analyse(i, m)
+        ref = orc.analyse(_olat(orc, lat), lat.get_state(i), m)
+        for k, r in ref.items():
+            assert abs(got[k] - r) <= 1e-12 * max(abs(r), 1e-3), (i, k, got[k], r)
+    lat.close()
+
+
+@pytest.mark.parametrize("n,prec,center", [(16, "fp64", "cell"), (32, "fp32", "origin"), (96, "fp64", "cell"),
+                                           (256, "fp32", "cell")])
+def test_momentum_radial_matches_oracle(itse, orc, n, prec, center):
+    a = 0.2
+    lat = itse.Lattice(n, a, 1.3, a / 4, kin=3, precision=prec, center=center, nstates=1)
+    dt = np.float32 if prec == "fp32" else np.float64
+    x = synth.axis_coords(n, a, center)
+    g = np.exp(-(x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2) / 2.0)
+    lat.set_state(0, (g + 0.1 * synth.random_state(n, 9)).astype(dt))
+    nb = min(40, n)
+    got = lat.momentum_radial(0, nb)
+    ref = orc.momentum_radial(_olat(orc, lat), lat.get_state(0), nb)
+    assert np.array_equal(got["count"], ref["count"])
+    tol = 1e-12 if prec == "fp64" else 1e-5
+    for k in ("p", "psi", "y"):
+        assert np.abs(got[k] - ref[k]).max() <= tol * np.abs(ref[k]).max(), k
+    lat.close()
+
+
+def test_analysis_rejects_bad_arguments(itse):
+    lat = itse.Lattice(16, 0.2, 1.3, 0.05, kin=3, precision="fp64", nstates=1)
+    lat.set_state(0, synth.random_state(16, 1))
+    for bad in (-0.1, 1.0):
+        with pytest.raises(itse.ItseError):
+            lat.analyse(0, bad)
+    with pytest.raises(itse.ItseError):
+        lat.momentum_radial(0, 0)
+    with pytest.raises(itse.ItseError):
+        lat.momentum_radial(0, 513)
+    lat.close()

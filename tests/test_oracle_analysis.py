@@ -1,0 +1,74 @@
+"""Pins for the oracle's analysis of a state: box normalisation and the average
+radius (section "Finite volume normalization"), parity weights (section "Parity
+projection"), and the radial momentum-space wave-function.
+
+Independent references: states of definite parity built from Gaussians (their
+weights are 0 or 1 by symmetry, mixtures by their norms), one-site states (the
+radius is the site's distance), the box's site count from its definition, and a
+single plane wave (all weight at one momentum shell, with the normalisation
+fixed in closed form)."""
+import numpy as np
+import pytest
+
+
+def _grid(n, a, center):
+    idx = np.arange(n, dtype=np.float64)
+    c = (idx - 0.5 * (n - 1)) * a if center == "cell" else np.where(2 * idx <= n, idx, idx - n) * a
+    return c[:, None, None], c[None, :, None], c[None, None, :]
+
+
+@pytest.mark.parametrize("center", ["cell", "origin"])
+def test_parity_weights_of_definite_states(orc, center):
+    n, a = 16, 0.3
+    L = orc.lattice(n, a, 1.0, center=center)
+    x, y, z = _grid(n, a, center)
+    g = np.exp(-(x * x + y * y + z * z) / 0.8)
+    even = orc.analyse(L, g, 0.3)
+    assert abs(even["w_plus"] - 1) < 1e-14 and even["w_minus"] < 1e-14
+    for k, odd in enumerate((x * g, y * g, z * g)):
+        w = orc.analyse(L, odd, 0.3)
+        assert abs(w["w_minus"] - 1) < 1e-14 and w["w_plus"] < 1e-14
+        for j in range(3):
+            expect = 1.0 if j == k else 0.0
+            assert abs(w[f"w_minus_e{j + 1}"] - expect) < 1e-14, (k, j)
+    # a mixture: weights are the shares of the norms inside the box
+    e, o = g, z * g
+    w = orc.analyse(L, 0.6 * e + 0.8 * o, 0.3)
+    ne, no = orc.analyse(L, e, 0.3)["box_norm2"], orc.analyse(L, o, 0.3)["box_norm2"]
+    share = 0.36 * ne / (0.36 * ne + 0.64 * no)
+    assert abs(w["w_plus"] - share) < 1e-13 and abs(w["w_minus"] - (1 - share)) < 1e-13
+
+
+def test_box_membership_and_radius(orc):
+    n, a = 16, 0.25
+    L = orc.lattice(n, a, 1.0, center="cell")
+    ones = np.ones((n, n, n))
+    # side (1 - m) N sites: m = 0.5 keeps indices 4..11 on each axis
+    assert orc.analyse(L, ones, 0.5)["box_norm2"] == 8 ** 3
+    assert orc.analyse(L, ones, 0.0)["box_norm2"] == n ** 3
+    one = np.zeros((n, n, n))
+    one[9, 5, 8] = 2.0
+    r = np.sqrt(1.5 ** 2 + 2.5 ** 2 + 0.5 ** 2)      # distance from the cell centre, lattice units
+    w = orc.analyse(L, one, 0.3)
+    assert abs(w["rho_box"] - r) < 1e-14 and abs(w["box_norm2"] - 4.0) < 1e-14
+
+
+def test_momentum_radial_plane_wave(orc):
+    n, a = 16, 0.2
+    L = orc.lattice(n, a, 1.0, center="cell")
+    x = np.arange(n)
+    psi = np.cos(2 * np.pi * x / n)[:, None, None] * np.ones((1, n, n))
+    out = orc.momentum_radial(L, psi, 12)
+    dp = 2 * np.pi / (n * a)
+    # shell counts from their definition: integer vectors m with round(|m|) = b
+    mm = np.where(2 * x <= n, x, x - n)
+    rad = np.sqrt(mm[:, None, None] ** 2 + mm[None, :, None] ** 2 + mm[None, None, :] ** 2)
+    shells = np.bincount(np.floor(rad + 0.5).astype(int).ravel())
+    assert np.array_equal(out["count"], shells[:12].astype(float))
+    # shell 1 holds |m| = 1 (6 vectors) and |m| = sqrt 2 (12 vectors)
+    assert out["count"][0] == 1 and out["count"][1] == 18
+    # all weight at p = +-dp along x: |Psi|^2 dp^3 = 1/2 each
+    assert abs(out["psi"][1] - 2 * (2 * dp ** 3) ** -0.5 / 18) < 1e-12
+    assert abs(out["p"][1] - dp * (6 + 12 * np.sqrt(2)) / 18) < 1e-12
+    assert abs(out["y"][1] - np.sqrt(4 * np.pi) * out["p"][1] * out["psi"][1]) < 1e-12
+    assert np.abs(out["psi"][np.arange(12) != 1]).max() < 1e-10
