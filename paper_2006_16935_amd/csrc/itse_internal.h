@@ -103,7 +103,9 @@ struct Launch {
     static hipError_t plane_fwd(int n, int variant, const JobRef *jobs, int njobs, hipStream_t s);
     static hipError_t columns(int n, int variant, int mode, int moments, const JobRef *jobs, int njobs, void *out,
                               hipStream_t s);
-    static hipError_t plane_inv(int n, int variant, int mode, const JobRef *jobs, int njobs, hipStream_t s);
+    // moments: some job's lattice sums position moments (else they are left at zero)
+    static hipError_t plane_inv(int n, int variant, int mode, int moments, const JobRef *jobs, int njobs,
+                                hipStream_t s);
     static hipError_t project(int n, const JobRef *jobs, int njobs, int force_sign, int force_axes, int which,
                               hipStream_t s);
     static hipError_t project_gram(int n, int kmax, const JobRef *lats, int nlats, int force, int which,

@@ -151,22 +151,28 @@ hipError_t Launch<R>::columns(int n, int variant, int mode, int moments, const J
 
 template <typename R>
 struct PlaneInvF {
-    int mode;
+    int mode, mom;
     const JobRef *jobs;
     int njobs;
     hipStream_t s;
     template <int N, int V>
     hipError_t operator()() {
         using G = Geo<R, N, V>;
-        hipLaunchKernelGGL((k_plane_inv<R, N, V>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0, s, jobs, mode);
+        if (mom)
+            hipLaunchKernelGGL((k_plane_inv<R, N, V, true>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0, s, jobs,
+                               mode);
+        else
+            hipLaunchKernelGGL((k_plane_inv<R, N, V, false>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0, s,
+                               jobs, mode);
         return hipGetLastError();
     }
 };
 
 template <typename R>
-hipError_t Launch<R>::plane_inv(int n, int variant, int mode, const JobRef *jobs, int njobs, hipStream_t s) {
+hipError_t Launch<R>::plane_inv(int n, int variant, int mode, int moments, const JobRef *jobs, int njobs,
+                                hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    return dispatch<R>(n, variant, PlaneInvF<R>{mode, jobs, njobs, s});
+    return dispatch<R>(n, variant, PlaneInvF<R>{mode, moments, jobs, njobs, s});
 }
 
 template <typename R>

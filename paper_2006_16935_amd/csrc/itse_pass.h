@@ -810,7 +810,9 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
 // mode INV_UPDATE: u_i <- ((1 - h V) psi - dtau K psi) / (1 + h V)   (= A psi - B dtau K psi)
 // mode INV_EVAL: sums only; INV_KOUT: K psi written to L.kout.
 // ---------------------------------------------------------------------------
-template <typename R, int N, int V>
+// MOM: position moments summed (the lattices' moments flag); without them the
+// update loop has the registers to take two chunks per load round.
+template <typename R, int N, int V, bool MOM>
 __global__ void __launch_bounds__((Geo<R, N, V>::NTP)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPE)))
 k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     using G = Geo<R, N, V>;
@@ -873,13 +875,13 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     ITSE_GLOBAL R *u = gmem((R *)state_buf(L, L.step, 1, i));
     ITSE_GLOBAL R *kout = gmem((R *)L.kout);
     const R h = (R)L.h, dt = (R)L.dtau;
-    const bool mom = L.moments != 0;
+    const bool mom = MOM && L.moments != 0;
     const int center = L.center;
     const double a = L.a;
     double acc[NQR];
 #pragma unroll
     for (int q = 0; q < NQR; ++q) acc[q] = 0.0;
-    using PC = PairChunks<R, N, PPW, 1>;
+    using PC = PairChunks<R, N, PPW, MOM ? 1 : 2>;
     constexpr int VL = PC::VL, GG = PC::G;
     const double cx = site_coord(x, N, center, a);
 #pragma unroll 1

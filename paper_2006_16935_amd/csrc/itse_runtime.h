@@ -11,11 +11,12 @@
 
 namespace itse {
 
-// Optional passes of a step: the one-state-at-a-time projection (states projected
-// along different axes) and the fused projection + Gram pass (any projection, or
-// Gram-Schmidt of more than one state).  A step without them only launches the
+// Optional work of a step: the one-state-at-a-time projection (states projected
+// along different axes), the fused projection + Gram pass (any projection, or
+// Gram-Schmidt of more than one state), and the position moments (the kernel
+// instance that sums them).  A step without the first two only launches the
 // transform passes and the finalisation.
-enum StepNeeds { NEED_PROJECT = 1, NEED_GRAM = 2 };
+enum StepNeeds { NEED_PROJECT = 1, NEED_GRAM = 2, NEED_MOMENTS = 4 };
 
 // A set of jobs of equal (n, precision, schedule) stepped by the same launches.
 struct Group {
@@ -25,7 +26,7 @@ struct Group {
     const JobRef *lats = nullptr;  // device array of (lattice, 0)
     int nlats = 0;
     int kmax = 1;                  // largest number of states among the lattices
-    int needs = NEED_PROJECT | NEED_GRAM;  // optional passes a step launches
+    int needs = NEED_PROJECT | NEED_GRAM | NEED_MOMENTS;  // optional work of a step
     bool fdtd = false;             // H_K^(0): one stencil pass instead of the transforms
 };
 

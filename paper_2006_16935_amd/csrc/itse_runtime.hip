@@ -349,13 +349,14 @@ static hipError_t seq_forward_kin(const Group &g, int inv_mode, hipStream_t s) {
     hipError_t e;
     if ((e = Launch<R>::plane_fwd(g.n, g.variant, g.jobs, g.njobs, s)) != hipSuccess) return e;
     if ((e = Launch<R>::columns(g.n, g.variant, COL_KIN, 1, g.jobs, g.njobs, nullptr, s)) != hipSuccess) return e;
-    return Launch<R>::plane_inv(g.n, g.variant, inv_mode, g.jobs, g.njobs, s);
+    return Launch<R>::plane_inv(g.n, g.variant, inv_mode, (g.needs & NEED_MOMENTS) ? 1 : 0, g.jobs, g.njobs, s);
 }
 
 int step_needs(const LatDev &o, int nstates) {
     int m = 0;
     if (o.proj_mode == 2) m |= NEED_PROJECT;
     if (o.proj_mode != 0 || (nstates > 1 && o.ortho_every > 0)) m |= NEED_GRAM;
+    if (o.moments) m |= NEED_MOMENTS;
     return m;
 }
 
@@ -1292,7 +1293,8 @@ static hipError_t launch_pass(const Group &g, int p, hipStream_t s) {
     case 1: return Launch<R>::columns(g.n, g.variant, COL_KIN, 1, g.jobs, g.njobs, nullptr, s);
     case 2:
         return g.fdtd ? Launch<R>::fdtd(g.n, g.kmax, INV_UPDATE, g.jobs, g.njobs, s)
-                      : Launch<R>::plane_inv(g.n, g.variant, INV_UPDATE, g.jobs, g.njobs, s);
+                      : Launch<R>::plane_inv(g.n, g.variant, INV_UPDATE, (g.needs & NEED_MOMENTS) ? 1 : 0, g.jobs,
+                                             g.njobs, s);
     case 3: return (g.needs & NEED_PROJECT) ? Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, 1, s) : hipSuccess;
     case 4:
         return (g.needs & NEED_GRAM) ? Launch<R>::project_gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s) : hipSuccess;
