@@ -100,11 +100,12 @@ struct Launch {
     static Sched schedule(int n, int variant);
     static int variants(int n);
     // Passes over a group of jobs sharing n; jobs is a device array of njobs entries.
-    static hipError_t plane_fwd(int n, int variant, const JobRef *jobs, int njobs, hipStream_t s);
+    // kmax: the largest number of states among the jobs' lattices
+    static hipError_t plane_fwd(int n, int variant, int kmax, const JobRef *jobs, int njobs, hipStream_t s);
     static hipError_t columns(int n, int variant, int mode, int moments, const JobRef *jobs, int njobs, void *out,
                               hipStream_t s);
     // moments: some job's lattice sums position moments (else they are left at zero)
-    static hipError_t plane_inv(int n, int variant, int mode, int moments, const JobRef *jobs, int njobs,
+    static hipError_t plane_inv(int n, int variant, int mode, int moments, int kmax, const JobRef *jobs, int njobs,
                                 hipStream_t s);
     static hipError_t project(int n, const JobRef *jobs, int njobs, int force_sign, int force_axes, int which,
                               hipStream_t s);

@@ -107,23 +107,36 @@ Sched Launch<R>::schedule(int n, int variant) {
     return out;
 }
 
+// Bound on the number of states of the lattices a plane-pass launch serves: the
+// instance with the smallest bound >= kmax (1, 4 or MAXK).
+template <typename F>
+static hipError_t with_state_bound(int kmax, F f) {
+    if (kmax <= 1) return f(std::integral_constant<int, 1>{});
+    if (kmax <= 4) return f(std::integral_constant<int, 4>{});
+    return f(std::integral_constant<int, MAXK>{});
+}
+
 template <typename R>
 struct PlaneFwdF {
+    int kmax;
     const JobRef *jobs;
     int njobs;
     hipStream_t s;
     template <int N, int V>
     hipError_t operator()() {
         using G = Geo<R, N, V>;
-        hipLaunchKernelGGL((k_plane_fwd<R, N, V>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0, s, jobs);
-        return hipGetLastError();
+        return with_state_bound(kmax, [&](auto kc) {
+            constexpr int KM = decltype(kc)::value;
+            hipLaunchKernelGGL((k_plane_fwd<R, N, V, KM>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0, s, jobs);
+            return hipGetLastError();
+        });
     }
 };
 
 template <typename R>
-hipError_t Launch<R>::plane_fwd(int n, int variant, const JobRef *jobs, int njobs, hipStream_t s) {
+hipError_t Launch<R>::plane_fwd(int n, int variant, int kmax, const JobRef *jobs, int njobs, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    return dispatch<R>(n, variant, PlaneFwdF<R>{jobs, njobs, s});
+    return dispatch<R>(n, variant, PlaneFwdF<R>{kmax, jobs, njobs, s});
 }
 
 template <typename R>
@@ -151,28 +164,31 @@ hipError_t Launch<R>::columns(int n, int variant, int mode, int moments, const J
 
 template <typename R>
 struct PlaneInvF {
-    int mode, mom;
+    int mode, mom, kmax;
     const JobRef *jobs;
     int njobs;
     hipStream_t s;
     template <int N, int V>
     hipError_t operator()() {
         using G = Geo<R, N, V>;
-        if (mom)
-            hipLaunchKernelGGL((k_plane_inv<R, N, V, true>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0, s, jobs,
-                               mode);
-        else
-            hipLaunchKernelGGL((k_plane_inv<R, N, V, false>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0, s,
-                               jobs, mode);
-        return hipGetLastError();
+        return with_state_bound(kmax, [&](auto kc) {
+            constexpr int KM = decltype(kc)::value;
+            if (mom)
+                hipLaunchKernelGGL((k_plane_inv<R, N, V, true, KM>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0,
+                                   s, jobs, mode);
+            else
+                hipLaunchKernelGGL((k_plane_inv<R, N, V, false, KM>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0,
+                                   s, jobs, mode);
+            return hipGetLastError();
+        });
     }
 };
 
 template <typename R>
-hipError_t Launch<R>::plane_inv(int n, int variant, int mode, int moments, const JobRef *jobs, int njobs,
+hipError_t Launch<R>::plane_inv(int n, int variant, int mode, int moments, int kmax, const JobRef *jobs, int njobs,
                                 hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    return dispatch<R>(n, variant, PlaneInvF<R>{mode, moments, jobs, njobs, s});
+    return dispatch<R>(n, variant, PlaneInvF<R>{mode, moments, kmax, jobs, njobs, s});
 }
 
 template <typename R>

@@ -279,19 +279,20 @@ __device__ __forceinline__ void block_sums(double (&acc)[Q], double *dst, double
     }
 }
 
-// Lattice fields used by the passes, copied out of the device record once.
-template <typename R>
+// Lattice fields used by the passes, copied out of the device record once; KM
+// bounds the number of states of the lattices a launch serves (i < KM).
+template <typename R, int KM = MAXK>
 struct LatView {
-    const ITSE_GLOBAL R *u[MAXK];
-    double c[MAXK];
+    const ITSE_GLOBAL R *u[KM];
+    double c[KM];
     int i;
 };
 
-template <typename R>
-__device__ __forceinline__ void load_view(LatView<R> &vw, const LatDev &L, int i) {
+template <typename R, int KM>
+__device__ __forceinline__ void load_view(LatView<R, KM> &vw, const LatDev &L, int i) {
     vw.i = i;
 #pragma unroll
-    for (int j = 0; j < MAXK; ++j) {
+    for (int j = 0; j < KM; ++j) {
         vw.u[j] = gmem((const R *)state_buf(L, L.step, 0, j));
         vw.c[j] = (j <= i) ? L.coef[j][i] : 0.0;
     }
@@ -299,11 +300,11 @@ __device__ __forceinline__ void load_view(LatView<R> &vw, const LatDev &L, int i
 
 // Current state psi_i at flat offset off: sum_(j<=i) coef[j][i] u_j in FP64,
 // rounded once to the storage precision.
-template <typename R>
-__device__ __forceinline__ R lazy_psi(const LatView<R> &vw, size_t off) {
+template <typename R, int KM>
+__device__ __forceinline__ R lazy_psi(const LatView<R, KM> &vw, size_t off) {
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < MAXK; ++j)
+    for (int j = 0; j < KM; ++j)
         if (j <= vw.i && vw.c[j] != 0.0) s += vw.c[j] * (double)vw.u[j][off];
     return (R)s;
 }
@@ -317,8 +318,8 @@ using Vec = R __attribute__((ext_vector_type(VLEN<R>)));
 // Current states of rows y0 and y1 of plane x over G chunks of VLEN consecutive
 // z (chunk t of the calling lane starts at z0[t]): psi = sum_(j<=i) c_j u_j in
 // FP64, rounded once.  All loads of one array are issued before any use.
-template <typename R, int G>
-__device__ __forceinline__ void lazy_rows(const LatView<R> &vw, const size_t (&o0)[G], const size_t (&o1)[G],
+template <typename R, int G, int KM>
+__device__ __forceinline__ void lazy_rows(const LatView<R, KM> &vw, const size_t (&o0)[G], const size_t (&o1)[G],
                                           const bool (&ok)[G], R (&p0)[G][VLEN<R>], R (&p1)[G][VLEN<R>]) {
     constexpr int VL = VLEN<R>;
     double a0[G][VL], a1[G][VL];
@@ -327,7 +328,7 @@ __device__ __forceinline__ void lazy_rows(const LatView<R> &vw, const size_t (&o
 #pragma unroll
         for (int k = 0; k < VL; ++k) a0[t][k] = a1[t][k] = 0.0;
 #pragma unroll
-    for (int j = 0; j < MAXK; ++j) {
+    for (int j = 0; j < KM; ++j) {
         if (j > vw.i) break;
         const double c = vw.c[j];
         if (c == 0.0) continue;
@@ -453,7 +454,7 @@ __device__ __forceinline__ void block_store_rows(const C2<R> *src, C2<R> *dst_, 
 // ---------------------------------------------------------------------------
 // P1: forward plane pass.  Sub-plane x * S + r and job from plane_block.
 // ---------------------------------------------------------------------------
-template <typename R, int N, int V>
+template <typename R, int N, int V, int KM>
 __global__ void __launch_bounds__((Geo<R, N, V>::NTP)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPE)))
 k_plane_fwd(const JobRef *__restrict__ jobs) {
     using G = Geo<R, N, V>;
@@ -468,14 +469,14 @@ k_plane_fwd(const JobRef *__restrict__ jobs) {
     const int x = spb / S, r = spb % S;
     const C2<R> *twg = (const C2<R> *)L.tw;
     for (int e = tid; e < N; e += G::NTP) tw[e] = twg[e];
-    LatView<R> vw;
+    LatView<R, KM> vw;
     load_view(vw, L, job.state);
     C2<R> *spec = (C2<R> *)L.spec[job.state];
 
     // rows of this wave's pairs -> packed complex rows (z along the line)
     const int p0 = wv * PPW;
     {
-        using PC = PairChunks<R, N, PPW, 2>;
+        using PC = PairChunks<R, N, PPW, KM <= 4 ? 4 : 2>;
         constexpr int VL = PC::VL, G = PC::G;
 #pragma unroll 1
         for (int gi = 0; gi < PC::GROUPS; ++gi) {
@@ -812,7 +813,7 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
 // ---------------------------------------------------------------------------
 // MOM: position moments summed (the lattices' moments flag); without them the
 // update loop has the registers to take two chunks per load round.
-template <typename R, int N, int V, bool MOM>
+template <typename R, int N, int V, bool MOM, int KM>
 __global__ void __launch_bounds__((Geo<R, N, V>::NTP)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPE)))
 k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     using G = Geo<R, N, V>;
@@ -869,7 +870,7 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     }
     WaveFft<R, N, PPW, +1, false, 1>::run(buf + p0 * LSZ, LSZ, 1, tw, lane);
     // update of this wave's rows
-    LatView<R> vw;
+    LatView<R, KM> vw;
     load_view(vw, L, i);
     const ITSE_GLOBAL R *v = gmem((const R *)L.v);
     ITSE_GLOBAL R *u = gmem((R *)state_buf(L, L.step, 1, i));
@@ -999,7 +1000,7 @@ struct FdGeo {
 // psi = sum_(j<=i) c_j u_j at one vector (FP64 combination, rounded once); KM
 // bounds the number of states (i < KM).
 template <typename R, int KM>
-__device__ __forceinline__ Vec<R> lazy_vec(const LatView<R> &vw, size_t off, bool ok) {
+__device__ __forceinline__ Vec<R> lazy_vec(const LatView<R, KM> &vw, size_t off, bool ok) {
     constexpr int VL = VLEN<R>;
     Vec<R> u[KM];
 #pragma unroll
@@ -1031,7 +1032,7 @@ __global__ void __launch_bounds__(NT) k_fdtd(const JobRef *__restrict__ jobs, in
     const JobRef job = jobs[jb];
     const LatDev &L = *job.lat;
     const int i = job.state;
-    LatView<R> vw;
+    LatView<R, KM> vw;
     load_view(vw, L, i);
     const ITSE_GLOBAL R *v = gmem((const R *)L.v);
     ITSE_GLOBAL R *u = gmem((R *)state_buf(L, L.step, 1, i));

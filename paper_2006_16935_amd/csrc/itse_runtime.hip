@@ -347,9 +347,10 @@ template <typename R>
 static hipError_t seq_forward_kin(const Group &g, int inv_mode, hipStream_t s) {
     if (g.fdtd) return Launch<R>::fdtd(g.n, g.kmax, inv_mode, g.jobs, g.njobs, s);
     hipError_t e;
-    if ((e = Launch<R>::plane_fwd(g.n, g.variant, g.jobs, g.njobs, s)) != hipSuccess) return e;
+    if ((e = Launch<R>::plane_fwd(g.n, g.variant, g.kmax, g.jobs, g.njobs, s)) != hipSuccess) return e;
     if ((e = Launch<R>::columns(g.n, g.variant, COL_KIN, 1, g.jobs, g.njobs, nullptr, s)) != hipSuccess) return e;
-    return Launch<R>::plane_inv(g.n, g.variant, inv_mode, (g.needs & NEED_MOMENTS) ? 1 : 0, g.jobs, g.njobs, s);
+    return Launch<R>::plane_inv(g.n, g.variant, inv_mode, (g.needs & NEED_MOMENTS) ? 1 : 0, g.kmax, g.jobs, g.njobs,
+                                s);
 }
 
 int step_needs(const LatDev &o, int nstates) {
@@ -1076,10 +1077,10 @@ extern "C" itse_status itse_spectrum(itse_lattice *L, int i, void *out) {
     Group g = state_group(L, i);
     hipError_t e;
     if (L->d.precision == ITSE_FP32) {
-        e = Launch<float>::plane_fwd(g.n, g.variant, g.jobs, 1, L->stream);
+        e = Launch<float>::plane_fwd(g.n, g.variant, g.kmax, g.jobs, 1, L->stream);
         if (e == hipSuccess) e = Launch<float>::columns(g.n, g.variant, COL_FWD, 0, g.jobs, 1, out, L->stream);
     } else {
-        e = Launch<double>::plane_fwd(g.n, g.variant, g.jobs, 1, L->stream);
+        e = Launch<double>::plane_fwd(g.n, g.variant, g.kmax, g.jobs, 1, L->stream);
         if (e == hipSuccess) e = Launch<double>::columns(g.n, g.variant, COL_FWD, 0, g.jobs, 1, out, L->stream);
     }
     if (e != hipSuccess) return fail(ITSE_EDEVICE, "spectrum launch: %s", hipGetErrorString(e));
@@ -1289,12 +1290,12 @@ namespace itse {
 template <typename R>
 static hipError_t launch_pass(const Group &g, int p, hipStream_t s) {
     switch (p) {
-    case 0: return Launch<R>::plane_fwd(g.n, g.variant, g.jobs, g.njobs, s);
+    case 0: return Launch<R>::plane_fwd(g.n, g.variant, g.kmax, g.jobs, g.njobs, s);
     case 1: return Launch<R>::columns(g.n, g.variant, COL_KIN, 1, g.jobs, g.njobs, nullptr, s);
     case 2:
         return g.fdtd ? Launch<R>::fdtd(g.n, g.kmax, INV_UPDATE, g.jobs, g.njobs, s)
-                      : Launch<R>::plane_inv(g.n, g.variant, INV_UPDATE, (g.needs & NEED_MOMENTS) ? 1 : 0, g.jobs,
-                                             g.njobs, s);
+                      : Launch<R>::plane_inv(g.n, g.variant, INV_UPDATE, (g.needs & NEED_MOMENTS) ? 1 : 0, g.kmax,
+                                             g.jobs, g.njobs, s);
     case 3: return (g.needs & NEED_PROJECT) ? Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, 1, s) : hipSuccess;
     case 4:
         return (g.needs & NEED_GRAM) ? Launch<R>::project_gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s) : hipSuccess;
