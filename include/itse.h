@@ -274,13 +274,23 @@ itse_status itse_batch_step(itse_batch *b, int nsteps);
 itse_status itse_batch_destroy(itse_batch *b);
 
 /* ---- schedules ------------------------------------------------------------------ */
+/* Schedules are kept per (n, precision) and per kind of lattice: one state, or
+ * several (their best schedules differ).  A lattice takes the schedule current at
+ * its creation.  Results stay deterministic for a given schedule. */
 /* Time the available transform schedules for (n, precision) on the current
- * device and keep the fastest for later lattices of that shape.  `json` (optional)
- * receives a description of the timings.  Results stay deterministic for a
- * given schedule. */
+ * device, on a three-state step (parity +, -, -, Gram-Schmidt) and on a bare
+ * one-state step, and keep the fastest of each for later lattices of that shape.
+ * `json` (optional) receives the timings ("times_ms", "times_ms_one_state") and
+ * the choices ("best", "best_one_state"). */
 itse_status itse_autotune(int n, int precision, void *hip_stream, char *json, size_t json_len);
+/* Description of the current multi-state schedule, with "variant_one_state". */
 itse_status itse_schedule_get(int n, int precision, char *json, size_t json_len);
+/* Set the schedule of both kinds of lattice; errors: ITSE_EINVAL for an unknown
+ * (n, precision) or variant. */
 itse_status itse_schedule_set(int n, int precision, int variant);
+/* Set the schedule of lattices with `nstates` states (1: one-state lattices,
+ * 2..ITSE_MAX_STATES: the multi-state ones). */
+itse_status itse_schedule_set_states(int n, int precision, int nstates, int variant);
 
 /* ---- serving: eigensolve requests with admission by HBM footprint ---------------- */
 /* A server owns the lattices of the requests it has admitted.  Requests wait in

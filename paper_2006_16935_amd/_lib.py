@@ -130,6 +130,7 @@ def load():
         "itse_autotune": ([ip, ip, vp, ctypes.c_char_p, ctypes.c_size_t], ip),
         "itse_schedule_get": ([ip, ip, ctypes.c_char_p, ctypes.c_size_t], ip),
         "itse_schedule_set": ([ip, ip, ip], ip),
+        "itse_schedule_set_states": ([ip, ip, ip, ip], ip),
         "itse_server_create": ([ctypes.c_size_t, ip, ip, vp, P(vp)], ip),
         "itse_server_destroy": ([vp], ip),
         "itse_server_submit": ([vp, P(Request), P(ctypes.c_uint64)], ip),

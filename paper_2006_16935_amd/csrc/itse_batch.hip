@@ -45,37 +45,56 @@ struct itse_batch {
 // ------------------------------------------------------------------------------------
 // Schedule registry (selected by itse_autotune / itse_schedule_set)
 // ------------------------------------------------------------------------------------
+// keyed by (n, precision, one-state lattice or not): the best schedule of a bare
+// one-state step differs from that of a multi-state step
 static std::mutex g_sched_mu;
-static std::map<std::pair<int, int>, int> g_sched;
+static std::map<std::tuple<int, int, int>, int> g_sched;
 
 namespace itse {
-int schedule_variant_for(int n, int prec) {
+int schedule_variant_for(int n, int prec, int nstates) {
     std::lock_guard<std::mutex> lk(g_sched_mu);
-    auto it = g_sched.find({n, prec});
+    auto it = g_sched.find({n, prec, nstates == 1 ? 1 : 0});
     return it == g_sched.end() ? 0 : it->second;
 }
 }  // namespace itse
 
-extern "C" itse_status itse_schedule_set(int n, int precision, int variant) {
+static itse_status check_variant(int n, int precision, int variant) {
     if (!prec_supported(n, precision)) return fail(ITSE_EINVAL, "n = %d not supported", n);
     const int nv = precision == ITSE_FP32 ? Launch<float>::variants(n) : Launch<double>::variants(n);
     if (variant < 0 || variant >= nv) return fail(ITSE_EINVAL, "variant %d of %d", variant, nv);
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_schedule_set(int n, int precision, int variant) {
+    itse_status st = check_variant(n, precision, variant);
+    if (st) return st;
     std::lock_guard<std::mutex> lk(g_sched_mu);
-    g_sched[{n, precision}] = variant;
+    g_sched[{n, precision, 0}] = variant;
+    g_sched[{n, precision, 1}] = variant;
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_schedule_set_states(int n, int precision, int nstates, int variant) {
+    itse_status st = check_variant(n, precision, variant);
+    if (st) return st;
+    if (nstates < 1 || nstates > MAXK) return fail(ITSE_EINVAL, "nstates = %d", nstates);
+    std::lock_guard<std::mutex> lk(g_sched_mu);
+    g_sched[{n, precision, nstates == 1 ? 1 : 0}] = variant;
     return ITSE_OK;
 }
 
 extern "C" itse_status itse_schedule_get(int n, int precision, char *json, size_t len) {
     if (!prec_supported(n, precision)) return fail(ITSE_EINVAL, "n = %d not supported", n);
-    const int v = schedule_variant_for(n, precision);
+    const int v = schedule_variant_for(n, precision, 2);
+    const int v1 = schedule_variant_for(n, precision, 1);
     Sched s = prec_schedule(n, precision, v);
     if (json && len) {
         snprintf(json, len,
                  "{\"n\": %d, \"precision\": %d, \"variant\": %d, \"variants\": %d, \"split\": %d, "
                  "\"plane_waves\": %d, \"cols_per_wg\": %d, \"cols_waves\": %d, \"wg_plane\": %d, "
-                 "\"wg_cols\": %d, \"lds_plane\": %d, \"lds_cols\": %d}",
+                 "\"wg_cols\": %d, \"lds_plane\": %d, \"lds_cols\": %d, \"variant_one_state\": %d}",
                  n, precision, v, precision == ITSE_FP32 ? Launch<float>::variants(n) : Launch<double>::variants(n),
-                 s.split, s.nwp, s.cols_w, s.nwc, s.nb_rows, s.nb_cols, s.lds_plane, s.lds_cols);
+                 s.split, s.nwp, s.cols_w, s.nwc, s.nb_rows, s.nb_cols, s.lds_plane, s.lds_cols, v1);
     }
     return ITSE_OK;
 }
@@ -224,78 +243,86 @@ extern "C" itse_status itse_batch_destroy(itse_batch *B) {
 // ------------------------------------------------------------------------------------
 // Autotuning: time every schedule variant for (n, precision) on a scratch lattice.
 // ------------------------------------------------------------------------------------
+// Mean time (ms) of a step of a lattice of `nstates` states under schedule
+// variant v: synthetic states, parity +, -, - and Gram-Schmidt every step for
+// several states (every kernel of a step runs), the bare step for one state.
+static itse_status time_variant(int n, int precision, int v, int nstates, void *stream, float *out_ms) {
+    {
+        std::lock_guard<std::mutex> lk(g_sched_mu);
+        g_sched[{n, precision, nstates == 1 ? 1 : 0}] = v;
+    }
+    itse_desc d{};
+    d.n = n;
+    d.a = 0.1;
+    d.mass = 1.0;
+    d.kin = ITSE_KIN_REL_LAT;
+    d.subtract_rest_mass = 1;
+    d.dtau = 0.025;
+    d.precision = precision;
+    d.center = ITSE_CENTER_ORIGIN;
+    d.nstates = nstates;
+    itse_lattice *L = nullptr;
+    itse_status st = itse_create(&d, stream, nullptr, nullptr, nullptr, &L);
+    if (st) return st;
+    const size_t n3 = (size_t)n * n * n;
+    std::vector<double> psi(n3);
+    for (int i = 0; i < d.nstates && !st; ++i) {
+        for (size_t e = 0; e < n3; ++e) psi[e] = std::sin(0.37 * (double)(e % 100003) * (i + 1)) + 0.1 * i;
+        st = itse_set_state(L, i, psi.data(), ITSE_DTYPE_F64, 0);
+    }
+    itse_step_opts o{};
+    o.ortho_every = nstates > 1 ? 1 : 0;
+    if (nstates > 1) {
+        o.parity[0] = 1;
+        for (int i = 1; i < nstates; ++i) o.parity[i] = -1;
+    }
+    for (int i = 0; i < ITSE_MAX_STATES; ++i) o.axes[i] = 7;
+    if (!st) st = itse_step(L, 3, &o);
+    const int reps = n >= 192 ? 10 : 30;
+    float ms = 1e30f;
+    for (int trial = 0; trial < 2 && !st; ++trial) {
+        hipEvent_t e0, e1;
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        (void)hipEventRecord(e0, (hipStream_t)stream);
+        st = itse_step(L, reps, nullptr);
+        (void)hipEventRecord(e1, (hipStream_t)stream);
+        (void)hipEventSynchronize(e1);
+        float t = 0.f;
+        (void)hipEventElapsedTime(&t, e0, e1);
+        ms = std::min(ms, t);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    if (!st) st = itse_sync(L);
+    itse_destroy(L);
+    *out_ms = ms / reps;
+    return st;
+}
+
 extern "C" itse_status itse_autotune(int n, int precision, void *stream, char *json, size_t len) {
     if (!prec_supported(n, precision)) return fail(ITSE_EINVAL, "n = %d not supported", n);
     const int nv = precision == ITSE_FP32 ? Launch<float>::variants(n) : Launch<double>::variants(n);
-    std::string rep = "{\"n\": " + std::to_string(n) + ", \"precision\": " + std::to_string(precision) +
-                      ", \"times_ms\": [";
-    int best = 0;
-    float best_ms = 1e30f;
-    for (int v = 0; v < nv; ++v) {
-        {
-            std::lock_guard<std::mutex> lk(g_sched_mu);
-            g_sched[{n, precision}] = v;
+    std::string rep = "{\"n\": " + std::to_string(n) + ", \"precision\": " + std::to_string(precision);
+    int best[2] = {0, 0};
+    for (int one = 0; one < 2; ++one) {
+        rep += one ? ", \"times_ms_one_state\": [" : ", \"times_ms\": [";
+        float best_ms = 1e30f;
+        for (int v = 0; v < nv; ++v) {
+            float ms = 0.f;
+            itse_status st = time_variant(n, precision, v, one ? 1 : 3, stream, &ms);
+            if (st) return st;
+            rep += (v ? ", " : "") + std::to_string(ms);
+            if (ms < best_ms) {
+                best_ms = ms;
+                best[one] = v;
+            }
         }
-        itse_desc d{};
-        d.n = n;
-        d.a = 0.1;
-        d.mass = 1.0;
-        d.kin = ITSE_KIN_REL_LAT;
-        d.subtract_rest_mass = 1;
-        d.dtau = 0.025;
-        d.precision = precision;
-        d.center = ITSE_CENTER_ORIGIN;
-        // three states (even, odd, odd deflated against the odd one): every kernel of
-        // a step runs, with distinct deterministic states so that the Gram matrix is
-        // well conditioned
-        d.nstates = 3;
-        itse_lattice *L = nullptr;
-        itse_status st = itse_create(&d, stream, nullptr, nullptr, nullptr, &L);
-        if (st) return st;
-        const size_t n3 = (size_t)n * n * n;
-        std::vector<double> psi(n3);
-        for (int i = 0; i < d.nstates && !st; ++i) {
-            for (size_t e = 0; e < n3; ++e) psi[e] = std::sin(0.37 * (double)(e % 100003) * (i + 1)) + 0.1 * i;
-            st = itse_set_state(L, i, psi.data(), ITSE_DTYPE_F64, 0);
-        }
-        itse_step_opts o{};
-        o.ortho_every = 1;
-        o.parity[0] = 1;
-        o.parity[1] = -1;
-        o.parity[2] = -1;
-        for (int i = 0; i < ITSE_MAX_STATES; ++i) o.axes[i] = 7;
-        if (!st) st = itse_step(L, 3, &o);
-        const int reps = n >= 192 ? 10 : 30;
-        float ms = 1e30f;
-        for (int trial = 0; trial < 2 && !st; ++trial) {
-            hipEvent_t e0, e1;
-            (void)hipEventCreate(&e0);
-            (void)hipEventCreate(&e1);
-            (void)hipEventRecord(e0, (hipStream_t)stream);
-            st = itse_step(L, reps, nullptr);
-            (void)hipEventRecord(e1, (hipStream_t)stream);
-            (void)hipEventSynchronize(e1);
-            float t = 0.f;
-            (void)hipEventElapsedTime(&t, e0, e1);
-            ms = std::min(ms, t);
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-        }
-        if (!st) st = itse_sync(L);
-        itse_destroy(L);
-        if (st) return st;
-        ms /= reps;
-        rep += (v ? ", " : "") + std::to_string(ms);
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = v;
-        }
-    }
-    {
+        rep += "]";
         std::lock_guard<std::mutex> lk(g_sched_mu);
-        g_sched[{n, precision}] = best;
+        g_sched[{n, precision, one}] = best[one];
     }
-    rep += "], \"best\": " + std::to_string(best) + "}";
+    rep += ", \"best\": " + std::to_string(best[0]) + ", \"best_one_state\": " + std::to_string(best[1]) + "}";
     if (json && len) snprintf(json, len, "%s", rep.c_str());
     return ITSE_OK;
 }

@@ -38,7 +38,7 @@ itse_status capture_steps(hipStream_t cap, const std::vector<Group> &groups, int
                           std::vector<hipStream_t> &branch, hipGraphExec_t *out);
 bool prec_supported(int n, int prec);
 Sched prec_schedule(int n, int prec, int variant);
-int schedule_variant_for(int n, int prec);
+int schedule_variant_for(int n, int prec, int nstates);
 double max_symbol(const itse_desc &d);
 itse_status norm_host(itse_lattice *L, int i, double *out);
 hipError_t launch_check_potential(const LatDev *lat, int prec, hipStream_t s);

@@ -553,7 +553,7 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
     L->alloc = alloc;
     L->freefn = free_fn;
     L->alloc_user = alloc_user;
-    L->variant = schedule_variant_for(d->n, d->precision);
+    L->variant = schedule_variant_for(d->n, d->precision, d->nstates);
     L->sched = prec_schedule(d->n, d->precision, L->variant);
     if (d->kin == ITSE_KIN_FDTD)
         L->sched.nb_rows = d->precision == ITSE_FP32 ? Launch<float>::fdtd_blocks(d->n)

@@ -332,9 +332,14 @@ def schedule(n: int, precision: str = "fp32") -> str:
     return buf.value.decode()
 
 
-def set_schedule(n: int, precision: str, variant: int):
-    """Select the transform schedule variant used by lattices created afterwards."""
-    check(_lib.load().itse_schedule_set(int(n), _PREC[precision], int(variant)))
+def set_schedule(n: int, precision: str, variant: int, nstates: Optional[int] = None):
+    """Select the transform schedule variant used by lattices created afterwards:
+    for all of them, or (nstates given) only for one-state (nstates = 1) or
+    multi-state lattices."""
+    if nstates is None:
+        check(_lib.load().itse_schedule_set(int(n), _PREC[precision], int(variant)))
+    else:
+        check(_lib.load().itse_schedule_set_states(int(n), _PREC[precision], int(nstates), int(variant)))
 
 
 def schedule_variants(n: int, precision: str = "fp32") -> int:
