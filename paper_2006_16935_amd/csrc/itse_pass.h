@@ -192,22 +192,6 @@ __device__ __forceinline__ int mirror_idx(int idx, int n, int center) {
     return center == ITSE_CENTER_CELL ? n - 1 - idx : (idx == 0 ? 0 : n - idx);
 }
 
-// Kinetic symbol from the sum of the three per-axis table entries (FP64):
-// non-relativistic forms use the sum directly; relativistic ones
-// sqrt(p^2 + m^2), or p^2 / (sqrt(p^2 + m^2) + m) = sqrt(p^2 + m^2) - m without
-// cancellation.
-__device__ __forceinline__ double kin_symbol(int kin, int sub, double mass, double s) {
-    if (kin == ITSE_KIN_NR_CONT || kin == ITSE_KIN_NR_LAT) return s;
-    const double e = sqrt(s + mass * mass);
-    return sub ? s / (e + mass) : e;
-}
-
-__device__ __forceinline__ float kin_symbol_f32(int kin, int sub, float mass, float s) {
-    if (kin == ITSE_KIN_NR_CONT || kin == ITSE_KIN_NR_LAT) return s;
-    const float e = sqrtf(s + mass * mass);
-    return sub ? s / (e + mass) : e;
-}
-
 // Kinetic symbol forms: the table sum itself (non-relativistic kinds),
 // sqrt(p^2 + m^2), and sqrt(p^2 + m^2) - m written as p^2 / (sqrt(p^2 + m^2) + m).
 enum SymKind { SYM_SUM = 0, SYM_REL = 1, SYM_REL_SUB = 2 };
@@ -690,20 +674,15 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
     }
     if (!fused) {
         WaveFft<R, N, LPW, -1, true, 1>::run(buf + l0, 1, CS, tw, lane);
+        // the same symbol evaluation as the line-wise paths (table sum over ky, kz
+        // first, then kx)
         auto multiply = [&](int kx, int ky, int kz, C2<R> &val) {
-            const double ssum = ktab[kx] + ktab[ky] + ktab[kz];
-            if constexpr (sizeof(R) == 4) {
-                // FP32 lattices: the symbol from the FP64 table sum, evaluated with
-                // correctly rounded FP32 operations (a few ulps, the transforms' own
-                // rounding level)
-                const float t = kin_symbol_f32(kin, rest, (float)mass, (float)ssum) * (float)inv_n3;
-                val.x = val.x * t;
-                val.y = val.y * t;
-            } else {
-                const double t = kin_symbol(kin, rest, mass, ssum) * inv_n3;
-                val.x = (R)((double)val.x * t);
-                val.y = (R)((double)val.y * t);
-            }
+            const double ssum = ktab[kx] + (ktab[ky] + ktab[kz]);
+            const R t = kind == SYM_SUM  ? symbol_scaled<R, SYM_SUM>(ssum, mass, inv_n3)
+                        : kind == SYM_REL ? symbol_scaled<R, SYM_REL>(ssum, mass, inv_n3)
+                                          : symbol_scaled<R, SYM_REL_SUB>(ssum, mass, inv_n3);
+            val.x *= t;
+            val.y *= t;
         };
         if (!mom) {
             if constexpr (64 % LPW == 0 && N % (64 / LPW) == 0) {

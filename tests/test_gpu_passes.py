@@ -51,6 +51,23 @@ def _olat(orc, lat):
                        "cell" if d.center == 0 else "origin")
 
 
+def test_schedule_per_kind(itse, orc):
+    """One-state and multi-state lattices keep their own schedules; each runs with
+    the one current at its creation."""
+    itse.set_schedule(256, "fp32", 4, nstates=1)
+    itse.set_schedule(256, "fp32", 3, nstates=3)
+    js = json.loads(itse.schedule(256, "fp32"))
+    assert js["variant"] == 3 and js["variant_one_state"] == 4
+    lat = _lat(itse, 256, "fp32", 4, kin=3)      # created under variant 4 (both kinds)
+    itse.set_schedule(256, "fp32", 0)
+    psi = synth.random_state(256, 17, dtype=np.float32)
+    lat.set_state(0, psi)
+    got = lat.apply_kinetic(0).cpu().numpy().astype(np.float64)
+    ref = orc.apply_kinetic(_olat(orc, lat), psi.astype(np.float64))
+    assert _rel(got, ref) < 2e-5
+    lat.close()
+
+
 @pytest.mark.parametrize("n,prec,variant", CASES)
 def test_spectrum_schedules(itse, orc, n, prec, variant):
     lat = _lat(itse, n, prec, variant)
