@@ -198,12 +198,15 @@ def test_projection_origin_axes(itse, orc, n, prec, parity, axes):
     lat.close()
 
 
-def test_precision_workload_first_steps(itse, orc):
-    """The 256^3 FP32 workload the benchmark times, in its default schedule: the
-    energies of the first steps match the FP64 oracle on the same FP32 inputs."""
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+def test_precision_workload_first_steps(itse, orc, variant):
+    """The 256^3 FP32 workload the benchmark times, in every schedule the autotuner
+    may pick: the energies of the first steps match the FP64 oracle on the same
+    FP32 inputs."""
     p = synth.config_precision(256)
     v = p.potential_array(np.float64).astype(np.float32)
     states = [s.astype(np.float32) for s in p.initial_states()]
+    itse.set_schedule(256, "fp32", variant)
     lat = itse.Lattice(p.n, p.a, p.mass, p.dtau, kin=p.kin, subtract_rest_mass=True,
                        precision="fp32", center=p.center, nstates=p.nstates)
     lat.set_potential(v)
@@ -219,4 +222,30 @@ def test_precision_workload_first_steps(itse, orc):
         for i in range(p.nstates):
             g, r = hist[s][i]["energy"], ohist[s][i]["energy"]
             assert abs(g - r) <= 1e-5 * abs(r), (s, i, g, r)
+    lat.close()
+
+
+@pytest.mark.parametrize("variant", [2, 4])
+def test_bare_one_state_steps(itse, orc, variant):
+    """The bare one-state 256^3 FP32 step of the benchmark (no projection, no
+    Gram-Schmidt): energies of the first steps and the state after them match the
+    FP64 oracle on the same FP32 inputs."""
+    p = synth.config_precision(256)
+    v = p.potential_array(np.float64).astype(np.float32)
+    psi = p.initial_states()[0].astype(np.float32)
+    itse.set_schedule(256, "fp32", variant, nstates=1)
+    lat = itse.Lattice(p.n, p.a, p.mass, p.dtau, kin=p.kin, subtract_rest_mass=True,
+                       precision="fp32", center=p.center, nstates=1)
+    itse.set_schedule(256, "fp32", 0)
+    lat.set_potential(v)
+    lat.set_state(0, psi)
+    lat.set_options(ortho_every=0)
+    steps = 3
+    lat.step(steps)
+    hist = lat.history(steps)
+    ostates, ohist = orc.step(_olat(orc, lat), [psi.astype(np.float64)], v.astype(np.float64), steps)
+    for s in range(steps):
+        g, r = hist[s][0]["energy"], ohist[s][0]["energy"]
+        assert abs(g - r) <= 1e-5 * abs(r), (s, g, r)
+    assert _rel(lat.get_state(0), ostates[0]) < 1e-4
     lat.close()
