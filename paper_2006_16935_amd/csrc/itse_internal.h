@@ -143,10 +143,15 @@ inline size_t spec_bytes(int n, int prec) {
     return (size_t)n * n * hs * 2 * w;
 }
 
-// Workgroups per plane of the projection/Gram kernel (about 4096 sites each).
+// Units per plane of the projection/Gram kernel (about 4096 sites each), and its
+// workgroups (at most 2048, each taking units in a stride; one partial each).
 inline int pg_chunks(int n) {
     const int c = n * n / 4096;
     return c < 1 ? 1 : c;
+}
+inline int pg_blocks(int n) {
+    const int u = n * pg_chunks(n);
+    return u < 2048 ? u : 2048;
 }
 
 inline int flat_blocks(int n) {

@@ -36,7 +36,7 @@ static Sched sched_of() {
     s.nb_rows = G::NB_PLANE;
     s.nb_cols = G::NB_COLS;
     s.nb_proj = N;
-    s.nb_gram = N * pg_chunks(N);
+    s.nb_gram = pg_blocks(N);
     s.lds_plane = (int)(G::PLANE_ELEMS * sizeof(C2<R>) + N * sizeof(C2<R>));
     s.lds_cols = (int)(N * G::CS * sizeof(C2<R>) + N * sizeof(C2<R>) + N * sizeof(double));
     return s;
@@ -203,7 +203,7 @@ template <typename R>
 hipError_t Launch<R>::project_gram(int n, int kmax, const JobRef *lats, int nlats, int force, int which,
                                    hipStream_t s) {
     if (nlats <= 0) return hipSuccess;
-    const dim3 grid(n * pg_chunks(n), nlats);
+    const dim3 grid(pg_blocks(n), nlats);
     if (kmax <= 4 && n / VLEN<R> <= 64) {
         // 16-byte form (rows of at most 64 vectors, up to four states)
         auto vec = [&](auto nc) -> hipError_t {

@@ -1182,100 +1182,103 @@ __global__ void __launch_bounds__(NT) k_project_gram(const JobRef *__restrict__ 
     if (!(ortho || (!force && L.proj_mode != 0)) || K > KM) return;  // finalize reads nothing then
     const int n = L.n, center = L.center;
     const int chunks = L.pg_chunks;
-    const int x = blockIdx.x / chunks, ch = blockIdx.x % chunks;
     const int axes = do_proj ? L.proj_axes : 0;
-    const int xm = (axes & 1) ? mirror_idx(x, n, center) : x;
     double acc[NGK];
 #pragma unroll
     for (int g = 0; g < NGK; ++g) acc[g] = 0.0;
     // threads along z (rows of n sites, NT / n rows at a time), rows [y0, y1) of plane x
     const int rpi = NT / n;
     const int z = threadIdx.x % n, ry = threadIdx.x / n;
-    if (xm >= x && ry < rpi) {
-        const size_t n2 = (size_t)n * n;
-        ITSE_GLOBAL R *ua[KM];
-        ITSE_GLOBAL R *ub[KM];
-        R sg[KM];
+    // units (plane x, chunk of rows), strided over the workgroups
+    for (int unit = blockIdx.x; unit < n * chunks; unit += gridDim.x) {
+        const int x = unit / chunks, ch = unit % chunks;
+        const int xm = (axes & 1) ? mirror_idx(x, n, center) : x;
+        if (xm >= x && ry < rpi) {
+            const size_t n2 = (size_t)n * n;
+            ITSE_GLOBAL R *ua[KM];
+            ITSE_GLOBAL R *ub[KM];
+            R sg[KM];
 #pragma unroll
-        for (int j = 0; j < KM; ++j) {
-            ITSE_GLOBAL R *u = gmem((R *)state_buf(L, L.step, which, j < K ? j : 0));
-            ua[j] = u + (size_t)x * n2;
-            ub[j] = u + (size_t)xm * n2;
-            sg[j] = (do_proj && j < K) ? (R)L.psign[j] : (R)0;
-        }
-        const int rpc = (n + chunks - 1) / chunks;
-        const int y0 = ch * rpc, y1 = y0 + rpc < n ? y0 + rpc : n;
-        const int zm = (axes & 4) ? mirror_idx(z, n, center) : z;
-        // rows in batches of RB, the loads of the next batch issued before the stores
-        // of the current one (stores and loads share the memory wait counter)
-        constexpr int RB = 4;
-        const int nrows = y0 + ry < y1 ? (y1 - (y0 + ry) + rpi - 1) / rpi : 0;
-        const int nbatch = (nrows + RB - 1) / RB;
-        R ca[RB][KM], cb[RB][KM];
-        auto load_batch = [&](int bi, R (&la)[RB][KM], R (&lb)[RB][KM]) {
-#pragma unroll
-            for (int t = 0; t < RB; ++t) {
-                const int k = bi * RB + t;
-                const int y = y0 + ry + k * rpi;
-                const int ym = (axes & 2) ? mirror_idx(y, n, center) : y;
-                const bool ok = k < nrows;
-                const int e = ok ? y * n + z : 0, m = ok ? ym * n + zm : 0;
-#pragma unroll
-                for (int j = 0; j < KM; ++j) {
-                    la[t][j] = (ok && j < K) ? ua[j][e] : (R)0;
-                    lb[t][j] = (ok && j < K) ? ub[j][m] : (R)0;
-                }
+            for (int j = 0; j < KM; ++j) {
+                ITSE_GLOBAL R *u = gmem((R *)state_buf(L, L.step, which, j < K ? j : 0));
+                ua[j] = u + (size_t)x * n2;
+                ub[j] = u + (size_t)xm * n2;
+                sg[j] = (do_proj && j < K) ? (R)L.psign[j] : (R)0;
             }
-        };
-        if (nbatch > 0) load_batch(0, ca, cb);
-        for (int bi = 0; bi < nbatch; ++bi) {
-            R na[RB][KM], nb[RB][KM];
-            if (bi + 1 < nbatch) load_batch(bi + 1, na, nb);
+            const int rpc = (n + chunks - 1) / chunks;
+            const int y0 = ch * rpc, y1 = y0 + rpc < n ? y0 + rpc : n;
+            const int zm = (axes & 4) ? mirror_idx(z, n, center) : z;
+            // rows in batches of RB, the loads of the next batch issued before the stores
+            // of the current one (stores and loads share the memory wait counter)
+            constexpr int RB = 4;
+            const int nrows = y0 + ry < y1 ? (y1 - (y0 + ry) + rpi - 1) / rpi : 0;
+            const int nbatch = (nrows + RB - 1) / RB;
+            R ca[RB][KM], cb[RB][KM];
+            auto load_batch = [&](int bi, R (&la)[RB][KM], R (&lb)[RB][KM]) {
 #pragma unroll
-            for (int t = 0; t < RB; ++t) {
-                const int k = bi * RB + t;
-                if (k >= nrows) continue;
-                const int y = y0 + ry + k * rpi;
-                const int ym = (axes & 2) ? mirror_idx(y, n, center) : y;
-                const int e = y * n + z, m = ym * n + zm;
-                const bool self = xm == x && m == e;
-                if (xm == x && m < e) continue;
-                double va[KM], vb[KM];
-#pragma unroll
-                for (int j = 0; j < KM; ++j) {
-                    va[j] = vb[j] = 0.0;
-                    if (j < K) {
-                        const R a = ca[t][j];
-                        const R b = self ? a : cb[t][j];
-                        R pa = a, pb = b;
-                        if (sg[j] != (R)0) {
-                            if (self) {
-                                pa = pb = sg[j] > (R)0 ? a : (R)0;
-                            } else {
-                                pa = (R)0.5 * (a + sg[j] * b);
-                                pb = sg[j] * pa;
-                            }
-                            ua[j][e] = pa;
-                            if (!self) ub[j][m] = pb;
-                        }
-                        va[j] = (double)pa;
-                        vb[j] = self ? 0.0 : (double)pb;
-                    }
-                }
-                int g = 0;
-#pragma unroll
-                for (int l = 0; l < KM; ++l)
-#pragma unroll
-                    for (int j = 0; j <= l; ++j) acc[g++] += va[j] * va[l] + vb[j] * vb[l];
-            }
-            if (bi + 1 < nbatch) {
-#pragma unroll
-                for (int t = 0; t < RB; ++t)
+                for (int t = 0; t < RB; ++t) {
+                    const int k = bi * RB + t;
+                    const int y = y0 + ry + k * rpi;
+                    const int ym = (axes & 2) ? mirror_idx(y, n, center) : y;
+                    const bool ok = k < nrows;
+                    const int e = ok ? y * n + z : 0, m = ok ? ym * n + zm : 0;
 #pragma unroll
                     for (int j = 0; j < KM; ++j) {
-                        ca[t][j] = na[t][j];
-                        cb[t][j] = nb[t][j];
+                        la[t][j] = (ok && j < K) ? ua[j][e] : (R)0;
+                        lb[t][j] = (ok && j < K) ? ub[j][m] : (R)0;
                     }
+                }
+            };
+            if (nbatch > 0) load_batch(0, ca, cb);
+            for (int bi = 0; bi < nbatch; ++bi) {
+                R na[RB][KM], nb[RB][KM];
+                if (bi + 1 < nbatch) load_batch(bi + 1, na, nb);
+#pragma unroll
+                for (int t = 0; t < RB; ++t) {
+                    const int k = bi * RB + t;
+                    if (k >= nrows) continue;
+                    const int y = y0 + ry + k * rpi;
+                    const int ym = (axes & 2) ? mirror_idx(y, n, center) : y;
+                    const int e = y * n + z, m = ym * n + zm;
+                    const bool self = xm == x && m == e;
+                    if (xm == x && m < e) continue;
+                    double va[KM], vb[KM];
+#pragma unroll
+                    for (int j = 0; j < KM; ++j) {
+                        va[j] = vb[j] = 0.0;
+                        if (j < K) {
+                            const R a = ca[t][j];
+                            const R b = self ? a : cb[t][j];
+                            R pa = a, pb = b;
+                            if (sg[j] != (R)0) {
+                                if (self) {
+                                    pa = pb = sg[j] > (R)0 ? a : (R)0;
+                                } else {
+                                    pa = (R)0.5 * (a + sg[j] * b);
+                                    pb = sg[j] * pa;
+                                }
+                                ua[j][e] = pa;
+                                if (!self) ub[j][m] = pb;
+                            }
+                            va[j] = (double)pa;
+                            vb[j] = self ? 0.0 : (double)pb;
+                        }
+                    }
+                    int g = 0;
+#pragma unroll
+                    for (int l = 0; l < KM; ++l)
+#pragma unroll
+                        for (int j = 0; j <= l; ++j) acc[g++] += va[j] * va[l] + vb[j] * vb[l];
+                }
+                if (bi + 1 < nbatch) {
+#pragma unroll
+                    for (int t = 0; t < RB; ++t)
+#pragma unroll
+                        for (int j = 0; j < KM; ++j) {
+                            ca[t][j] = na[t][j];
+                            cb[t][j] = nb[t][j];
+                        }
+                }
             }
         }
     }
@@ -1312,9 +1315,7 @@ __global__ void __launch_bounds__(NT) k_project_gram_vec(const JobRef *__restric
     if (!(ortho || (!force && L.proj_mode != 0)) || K > KM) return;  // finalize reads nothing then
     const int center = L.center;
     const int chunks = L.pg_chunks;
-    const int x = blockIdx.x / chunks, ch = blockIdx.x % chunks;
     const int axes = do_proj ? L.proj_axes : 0;
-    const int xm = (axes & 1) ? mirror_idx(x, N, center) : x;
     const bool zr = (axes & 4) != 0;
     const bool origin_z = zr && center != ITSE_CENTER_CELL;
     double acc[NGK];
@@ -1333,92 +1334,97 @@ __global__ void __launch_bounds__(NT) k_project_gram_vec(const JobRef *__restric
         sg[j] = (do_proj && j < K) ? (R)L.psign[j] : (R)0;
     }
     const int rpc = (N + chunks - 1) / chunks;
-    const int y0 = ch * rpc, y1 = y0 + rpc < N ? y0 + rpc : N;
-    const bool active = xm >= x && slot < RPW;
-    // row slots of the workgroup step through the chunk's rows together (the
-    // shuffles below need every lane of the wave)
     constexpr int SLOTS = NWV * RPW;
-    for (int yb = y0; yb < y1; yb += SLOTS * RB) {
-        Vec<R> va[RB][KM], vb[RB][KM];
-        size_t oa[RB], ob[RB];
-        bool ok[RB], self[RB];
+    // units (plane x, chunk of rows), strided over the workgroups (uniform per
+    // workgroup, so every lane of a wave reaches the shuffles below)
+    for (int unit = blockIdx.x; unit < N * chunks; unit += gridDim.x) {
+        const int x = unit / chunks, ch = unit % chunks;
+        const int xm = (axes & 1) ? mirror_idx(x, N, center) : x;
+        const int y0 = ch * rpc, y1 = y0 + rpc < N ? y0 + rpc : N;
+        const bool active = xm >= x && slot < RPW;
+        // row slots of the workgroup step through the chunk's rows together
+        for (int yb = y0; yb < y1; yb += SLOTS * RB) {
+            Vec<R> va[RB][KM], vb[RB][KM];
+            size_t oa[RB], ob[RB];
+            bool ok[RB], self[RB];
 #pragma unroll
-        for (int t = 0; t < RB; ++t) {
-            const int y = yb + (t * NWV + wv) * RPW + slot;
-            const int ym = (axes & 2) ? mirror_idx(y < N ? y : 0, N, center) : y;
-            ok[t] = active && y < y1 && (xm != x || y <= ym);
-            self[t] = xm == x && y == ym;
-            oa[t] = ok[t] ? ((size_t)x * N + y) * N + (size_t)g * VL : 0;
-            ob[t] = ok[t] ? ((size_t)xm * N + ym) * N + (size_t)gb * VL : 0;
+            for (int t = 0; t < RB; ++t) {
+                const int y = yb + (t * NWV + wv) * RPW + slot;
+                const int ym = (axes & 2) ? mirror_idx(y < N ? y : 0, N, center) : y;
+                ok[t] = active && y < y1 && (xm != x || y <= ym);
+                self[t] = xm == x && y == ym;
+                oa[t] = ok[t] ? ((size_t)x * N + y) * N + (size_t)g * VL : 0;
+                ob[t] = ok[t] ? ((size_t)xm * N + ym) * N + (size_t)gb * VL : 0;
 #pragma unroll
-            for (int j = 0; j < KM; ++j) {
-                if (ok[t] && j < K) {
-                    va[t][j] = *(const ITSE_GLOBAL Vec<R> *)(uj[j] + oa[t]);
-                    vb[t][j] = *(const ITSE_GLOBAL Vec<R> *)(uj[j] + ob[t]);
-                } else {
-                    va[t][j] = Vec<R>{};
-                    vb[t][j] = Vec<R>{};
+                for (int j = 0; j < KM; ++j) {
+                    if (ok[t] && j < K) {
+                        va[t][j] = *(const ITSE_GLOBAL Vec<R> *)(uj[j] + oa[t]);
+                        vb[t][j] = *(const ITSE_GLOBAL Vec<R> *)(uj[j] + ob[t]);
+                    } else {
+                        va[t][j] = Vec<R>{};
+                        vb[t][j] = Vec<R>{};
+                    }
                 }
             }
-        }
 #pragma unroll
-        for (int t = 0; t < RB; ++t) {
-            double da[KM][VL], db[KM][VL];
+            for (int t = 0; t < RB; ++t) {
+                double da[KM][VL], db[KM][VL];
 #pragma unroll
-            for (int j = 0; j < KM; ++j) {
-                // mirror values of this lane's A and B sites
-                R ma[VL], mb[VL];
-                if (origin_z) {
-                    const R b0 = __shfl(vb[t][j][0], src_prev, 64);
-                    const R a0 = __shfl(va[t][j][0], src_next, 64);
-                    ma[0] = b0;
-                    mb[0] = a0;
+                for (int j = 0; j < KM; ++j) {
+                    // mirror values of this lane's A and B sites
+                    R ma[VL], mb[VL];
+                    if (origin_z) {
+                        const R b0 = __shfl(vb[t][j][0], src_prev, 64);
+                        const R a0 = __shfl(va[t][j][0], src_next, 64);
+                        ma[0] = b0;
+                        mb[0] = a0;
 #pragma unroll
-                    for (int k = 1; k < VL; ++k) {
-                        ma[k] = vb[t][j][VL - k];
-                        mb[k] = va[t][j][VL - k];
+                        for (int k = 1; k < VL; ++k) {
+                            ma[k] = vb[t][j][VL - k];
+                            mb[k] = va[t][j][VL - k];
+                        }
+                    } else if (zr) {
+#pragma unroll
+                        for (int k = 0; k < VL; ++k) {
+                            ma[k] = vb[t][j][VL - 1 - k];
+                            mb[k] = va[t][j][VL - 1 - k];
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < VL; ++k) {
+                            ma[k] = vb[t][j][k];
+                            mb[k] = va[t][j][k];
+                        }
                     }
-                } else if (zr) {
+                    Vec<R> pa = va[t][j], pb = vb[t][j];
+                    if (sg[j] != (R)0) {
+#pragma unroll
+                        for (int k = 0; k < VL; ++k) {
+                            pa[k] = (R)0.5 * (va[t][j][k] + sg[j] * ma[k]);
+                            pb[k] = (R)0.5 * (vb[t][j][k] + sg[j] * mb[k]);
+                        }
+                        if (ok[t]) {
+                            *(ITSE_GLOBAL Vec<R> *)(uj[j] + oa[t]) = pa;
+                            if (!self[t]) *(ITSE_GLOBAL Vec<R> *)(uj[j] + ob[t]) = pb;
+                        }
+                    }
+                    const bool use_b = ok[t] && !self[t];
 #pragma unroll
                     for (int k = 0; k < VL; ++k) {
-                        ma[k] = vb[t][j][VL - 1 - k];
-                        mb[k] = va[t][j][VL - 1 - k];
-                    }
-                } else {
-#pragma unroll
-                    for (int k = 0; k < VL; ++k) {
-                        ma[k] = vb[t][j][k];
-                        mb[k] = va[t][j][k];
+                        da[j][k] = ok[t] && j < K ? (double)pa[k] : 0.0;
+                        db[j][k] = use_b && j < K ? (double)pb[k] : 0.0;
                     }
                 }
-                Vec<R> pa = va[t][j], pb = vb[t][j];
-                if (sg[j] != (R)0) {
+                int q = 0;
 #pragma unroll
-                    for (int k = 0; k < VL; ++k) {
-                        pa[k] = (R)0.5 * (va[t][j][k] + sg[j] * ma[k]);
-                        pb[k] = (R)0.5 * (vb[t][j][k] + sg[j] * mb[k]);
-                    }
-                    if (ok[t]) {
-                        *(ITSE_GLOBAL Vec<R> *)(uj[j] + oa[t]) = pa;
-                        if (!self[t]) *(ITSE_GLOBAL Vec<R> *)(uj[j] + ob[t]) = pb;
-                    }
-                }
-                const bool use_b = ok[t] && !self[t];
+                for (int l = 0; l < KM; ++l)
 #pragma unroll
-                for (int k = 0; k < VL; ++k) {
-                    da[j][k] = ok[t] && j < K ? (double)pa[k] : 0.0;
-                    db[j][k] = use_b && j < K ? (double)pb[k] : 0.0;
-                }
+                    for (int j = 0; j <= l; ++j) {
+#pragma unroll
+                        for (int k = 0; k < VL; ++k) acc[q] += da[j][k] * da[l][k] + db[j][k] * db[l][k];
+                        ++q;
+                    }
             }
-            int q = 0;
-#pragma unroll
-            for (int l = 0; l < KM; ++l)
-#pragma unroll
-                for (int j = 0; j <= l; ++j) {
-#pragma unroll
-                    for (int k = 0; k < VL; ++k) acc[q] += da[j][k] * da[l][k] + db[j][k] * db[l][k];
-                    ++q;
-                }
         }
     }
     // slot layout l (l + 1) / 2 + j, the same for every KM
