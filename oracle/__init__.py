@@ -288,3 +288,37 @@ def momentum_radial(L: Lattice, psi: np.ndarray, nbins: int) -> dict:
         pmean = np.where(cnt > 0, ps / cnt, 0.0)
         fmean = np.where(cnt > 0, fs / cnt, 0.0)
     return {"count": cnt, "p": pmean, "psi": fmean, "y": np.sqrt(4 * np.pi) * pmean * fmean}
+
+
+# ---------------------------------------------------------------------------------
+# Complex potentials and wave-functions (plain numpy over the pinned real kinetic
+# operator): the map of equation iter_proced with complex V, A and B.
+# ---------------------------------------------------------------------------------
+def step_complex(L: Lattice, psi: np.ndarray, v: np.ndarray, nsteps: int, parity: int = 0, axes: int = 7,
+                 record: bool = True):
+    """One complex state, `nsteps` steps of psi' = A psi - B dtau H_K psi with
+    A = (1 - dtau V/2)/(1 + dtau V/2), B = 1/(1 + dtau V/2) for complex V (section
+    "The iterative procedure"; complex potentials are among the paper's inputs).
+    H_K is real and acts on the real and imaginary parts separately.  Per step:
+    observables of the current state (energy = <psi|H|psi>/<psi|psi>, complex:
+    "energy" its real part, "energy_imag" its imaginary part, "kinetic",
+    "norm2"), the update, the optional reflection projection (sign `parity`) of
+    both parts, and normalisation to sum |psi|^2 = 1.  Returns (psi, records)."""
+    psi = np.asarray(psi, dtype=np.complex128).copy()
+    v = np.asarray(v, dtype=np.complex128)
+    h = 0.5 * L.dtau
+    A = (1.0 - h * v) / (1.0 + h * v)
+    B = 1.0 / (1.0 + h * v)
+    recs = []
+    for _ in range(nsteps):
+        kp = apply_kinetic(L, psi.real) + 1j * apply_kinetic(L, psi.imag)
+        if record:
+            nn = float((np.abs(psi) ** 2).sum())
+            kin = float((psi.real * kp.real + psi.imag * kp.imag).sum()) / nn
+            pot = complex((v * np.abs(psi) ** 2).sum()) / nn
+            recs.append({"energy": kin + pot.real, "energy_imag": pot.imag, "kinetic": kin, "norm2": nn})
+        psi = A * psi - B * L.dtau * kp
+        if parity:
+            psi = project(L, psi.real, parity, axes) + 1j * project(L, psi.imag, parity, axes)
+        psi /= np.sqrt((np.abs(psi) ** 2).sum())
+    return psi, recs

@@ -252,3 +252,38 @@ def test_snapshot_extraction_plane_waves(orc):
         assert abs(obs[i]["energy"] - (q[i] ** 2) @ T) < 1e-12
     # the estimates approach the eigenstates in order of energy
     assert obs[0]["energy"] < obs[1]["energy"] < obs[2]["energy"]
+
+
+def test_complex_map_reduces_to_real(orc):
+    """Complex map with a real potential and a real state is the real map."""
+    n, a = 12, 0.3
+    L = orc.lattice(n, a, 1.2, dtau=a * a * 1.2 / 8, kin=2, center="cell")
+    v = synth.potential_harmonic(n, a, "cell", 0.5)
+    psi = synth.random_state(n, 3)
+    out_c, rec_c = orc.step_complex(L, psi, v, 5)
+    out_r, rec_r = orc.step(L, [psi], v, 5)
+    assert np.abs(out_c.imag).max() == 0.0
+    assert np.abs(out_c.real - out_r[0]).max() < 1e-14
+    for s in range(5):
+        assert abs(rec_c[s]["energy"] - rec_r[s][0]["energy"]) < 1e-13
+        assert rec_c[s]["energy_imag"] == 0.0
+
+
+def test_complex_constant_potential_closed_form(orc):
+    """Closed form: with a constant complex V0 a plane wave is an eigenvector of the
+    map with lambda = (1 - dtau V0/2 - dtau T(k)) / (1 + dtau V0/2); after n
+    normalised steps the state is the start times (lambda/|lambda|)^n, and its
+    energy is T(k) + V0."""
+    n, a, m, dtau = 12, 0.25, 1.0, 0.01
+    L = orc.lattice(n, a, m, dtau=dtau, kin=1, center="cell")
+    v0 = 0.7 - 0.3j
+    idx = np.indices((n, n, n))
+    mv = (2, 1, 0)
+    wave = np.cos(2 * np.pi * (mv[0] * idx[0] + mv[1] * idx[1] + mv[2] * idx[2]) / n)
+    wave /= np.linalg.norm(wave)
+    T = orc.kinetic_symbol(L)[mv]
+    lam = (1 - 0.5 * dtau * v0 - dtau * T) / (1 + 0.5 * dtau * v0)
+    out, rec = orc.step_complex(L, wave.astype(complex), np.full((n, n, n), v0), 7)
+    assert np.abs(out - (lam / abs(lam)) ** 7 * wave).max() < 1e-13
+    for r in rec:
+        assert abs(r["energy"] - (T + v0.real)) < 1e-12 and abs(r["energy_imag"] - v0.imag) < 1e-12
