@@ -92,6 +92,13 @@ typedef struct {
     int precision;           /* itse_precision                                        */
     int center;              /* itse_center: coordinates of moments and mirror sites  */
     int nstates;             /* number of states evolved together, 1..ITSE_MAX_STATES */
+    int complex_psi;         /* 1: one complex state (nstates must be 1) in a complex */
+                             /* potential V = Re V + i Im V (itse_set_potential sets  */
+                             /* Re V, itse_set_potential_imag Im V); the state is held */
+                             /* as two real arrays, state index 0 = Re psi and 1 =    */
+                             /* Im psi in itse_set_state / itse_get_state /           */
+                             /* itse_apply_kinetic / itse_spectrum; observables under  */
+                             /* index 0 only.  0: real states (zero-initialise).      */
 } itse_desc;
 
 /* Observables of one state at the start of a step (the paper's UPDATE output). */
@@ -104,7 +111,12 @@ typedef struct {
     double x, y, z, r2;      /* <x1>, <x2>, <x3>, <r^2> about the potential centre    */
                              /* (filled when moments were requested, else 0)          */
     double parity_even;      /* weight of P^+ psi: (1 + <psi|P psi>/<psi|psi>)/2      */
-                             /* (filled when moments were requested, else -1)         */
+                             /* (filled when moments were requested, else -1; -1 for  */
+                             /* H_K^(0) lattices: itse_analyse with min_sep_edge = 0  */
+                             /* gives it as w_plus)                                   */
+    double energy_imag;      /* complex states: Im <psi|H psi>/<psi|psi> = <psi|Im V    */
+                             /* psi>/<psi|psi> (energy, potential hold the real parts);*/
+                             /* 0 for real states                                      */
 } itse_obs;
 
 /* Per-lattice step options. */
@@ -116,6 +128,8 @@ typedef struct {
     int parity[ITSE_MAX_STATES];       /* per state: 0 none, +1 / -1 reflection projection*/
     int axes[ITSE_MAX_STATES];         /* reflected axes, bit0 x1, bit1 x2, bit2 x3;      */
                                        /* 7 = inversion (P^+-), 4 / 2 = INITSYMMETRY x3/x2*/
+                                       /* complex lattices: parity[0] / axes[0] project   */
+                                       /* Re psi and Im psi alike; ortho_every ignored    */
 } itse_step_opts;
 
 typedef void *(*itse_alloc_fn)(size_t bytes, void *user);
@@ -147,6 +161,13 @@ itse_status itse_set_stream(itse_lattice *lat, void *hip_stream);
  * host input only; device input is checked on the device at the next step). */
 itse_status itse_set_potential(itse_lattice *lat, const void *v, int dtype, int on_device);
 
+/* Imaginary part of the potential of a complex lattice (desc.complex_psi = 1),
+ * N^3 values; the step uses A = (1 - dtau V/2)/(1 + dtau V/2) and
+ * B = 1/(1 + dtau V/2) with the complex V (equation iter_proced; the paper's
+ * complex harmonic oscillator is such a potential).  Rejects non-finite values
+ * (ITSE_ENONFINITE, host input only) and real lattices (ITSE_ESTATE). */
+itse_status itse_set_potential_imag(itse_lattice *lat, const void *v, int dtype, int on_device);
+
 /* State i (0-based), N^3 values, any normalisation (the next step normalises). */
 itse_status itse_set_state(itse_lattice *lat, int i, const void *psi, int dtype, int on_device);
 
@@ -159,7 +180,10 @@ itse_status itse_set_step_opts(itse_lattice *lat, const itse_step_opts *opts);
 /* nsteps applications of the step map to every state, each followed by the
  * optional reflection projection, then Gram-Schmidt / normalisation
  * (order: update, projection, Gram-Schmidt in state order, normalise).
- * Observables of each state at the start of each step are recorded. */
+ * Observables of each state at the start of each step are recorded.  A complex
+ * lattice takes the map with complex A and B, the projection of both parts and
+ * the normalisation sum |Re psi|^2 + |Im psi|^2 = 1; it records one observable
+ * per step (index 0) with energy_imag. */
 itse_status itse_step(itse_lattice *lat, int nsteps, const itse_step_opts *opts);
 
 /* Observables of the current states without stepping (no update). */
@@ -173,6 +197,11 @@ itse_status itse_observe(itse_lattice *lat, int i, itse_obs *out);
 itse_status itse_history(itse_lattice *lat, int count, itse_obs *out);
 
 long long itse_step_count(const itse_lattice *lat);
+
+/* Entry points for real states only (ITSE_ESTATE on a complex lattice):
+ * itse_orthogonalise, itse_project_parity, itse_polish, itse_analyse,
+ * itse_momentum_radial, itse_snapshot_push, itse_snapshot_extract; and the
+ * server takes real states only. */
 
 /* Modified Gram-Schmidt of state i against states 0..i-1, then normalise. */
 itse_status itse_orthogonalise(itse_lattice *lat, int i);

@@ -295,14 +295,15 @@ def momentum_radial(L: Lattice, psi: np.ndarray, nbins: int) -> dict:
 # operator): the map of equation iter_proced with complex V, A and B.
 # ---------------------------------------------------------------------------------
 def step_complex(L: Lattice, psi: np.ndarray, v: np.ndarray, nsteps: int, parity: int = 0, axes: int = 7,
-                 record: bool = True):
+                 record: bool = True, moments: bool = False):
     """One complex state, `nsteps` steps of psi' = A psi - B dtau H_K psi with
     A = (1 - dtau V/2)/(1 + dtau V/2), B = 1/(1 + dtau V/2) for complex V (section
     "The iterative procedure"; complex potentials are among the paper's inputs).
     H_K is real and acts on the real and imaginary parts separately.  Per step:
     observables of the current state (energy = <psi|H|psi>/<psi|psi>, complex:
     "energy" its real part, "energy_imag" its imaginary part, "kinetic",
-    "norm2"), the update, the optional reflection projection (sign `parity`) of
+    "potential" the real part of <psi|V psi>/<psi|psi>, "norm2"; with `moments`
+    also "x", "y", "z", "r2" and "parity_even" of |psi|^2), the update, the optional reflection projection (sign `parity`) of
     both parts, and normalisation to sum |psi|^2 = 1.  Returns (psi, records)."""
     psi = np.asarray(psi, dtype=np.complex128).copy()
     v = np.asarray(v, dtype=np.complex128)
@@ -316,9 +317,27 @@ def step_complex(L: Lattice, psi: np.ndarray, v: np.ndarray, nsteps: int, parity
             nn = float((np.abs(psi) ** 2).sum())
             kin = float((psi.real * kp.real + psi.imag * kp.imag).sum()) / nn
             pot = complex((v * np.abs(psi) ** 2).sum()) / nn
-            recs.append({"energy": kin + pot.real, "energy_imag": pot.imag, "kinetic": kin, "norm2": nn})
+            rec = {"energy": kin + pot.real, "energy_imag": pot.imag, "kinetic": kin, "potential": pot.real,
+                   "norm2": nn}
+            if moments:
+                rec.update(_complex_moments(L, psi, v))
+            recs.append(rec)
         psi = A * psi - B * L.dtau * kp
         if parity:
             psi = project(L, psi.real, parity, axes) + 1j * project(L, psi.imag, parity, axes)
         psi /= np.sqrt((np.abs(psi) ** 2).sum())
     return psi, recs
+
+
+def _complex_moments(L: Lattice, psi: np.ndarray, v: np.ndarray) -> dict:
+    """Moments of |psi|^2 = Re^2 + Im^2 from those of the two real parts (each
+    normalised by its own norm), weighted by the parts' norms; the parity weight
+    from <psi|P psi> = <Re|P Re> + <Im|P Im> (the cross terms cancel under the
+    sum over sites because P is an involution)."""
+    o = observe(L, [psi.real, psi.imag], v.real)
+    w = [o[0]["norm2"], o[1]["norm2"]]
+    tot = w[0] + w[1]
+    out = {k: sum(o[t][k] * w[t] for t in range(2) if w[t] > 0) / tot for k in ("x", "y", "z", "r2")}
+    par = sum((2.0 * o[t]["parity_even"] - 1.0) * w[t] for t in range(2) if w[t] > 0)
+    out["parity_even"] = 0.5 * (1.0 + par / tot)
+    return out

@@ -29,10 +29,10 @@ class Desc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("a", ctypes.c_double), ("mass", ctypes.c_double),
                 ("dtau", ctypes.c_double), ("kin", ctypes.c_int),
                 ("subtract_rest_mass", ctypes.c_int), ("precision", ctypes.c_int),
-                ("center", ctypes.c_int), ("nstates", ctypes.c_int)]
+                ("center", ctypes.c_int), ("nstates", ctypes.c_int), ("complex_psi", ctypes.c_int)]
 
 
-OBS_FIELDS = ("energy", "kinetic", "potential", "norm2", "x", "y", "z", "r2", "parity_even")
+OBS_FIELDS = ("energy", "kinetic", "potential", "norm2", "x", "y", "z", "r2", "parity_even", "energy_imag")
 
 
 class Analysis(ctypes.Structure):
@@ -103,6 +103,7 @@ def load():
         "itse_destroy": ([vp], ip),
         "itse_set_stream": ([vp, vp], ip),
         "itse_set_potential": ([vp, vp, ip, ip], ip),
+        "itse_set_potential_imag": ([vp, vp, ip, ip], ip),
         "itse_set_state": ([vp, ip, vp, ip, ip], ip),
         "itse_get_state": ([vp, ip, vp, ip, ip], ip),
         "itse_set_step_opts": ([vp, P(StepOpts)], ip),

@@ -128,11 +128,13 @@ extern "C" itse_status itse_batch_create(int count, itse_lattice *const *lats, v
         delete B;
         return st;
     };
-    // group by (n, precision, variant, H_K^(0) or not), keeping input order within a group
+    // group by (n, precision, variant, kind: bit0 H_K^(0), bit1 complex), keeping
+    // input order within a group
     std::map<std::tuple<int, int, int, int>, std::vector<itse_lattice *>> by;
     std::vector<std::tuple<int, int, int, int>> order;
     for (auto *L : B->lats) {
-        auto key = std::make_tuple(L->d.n, L->d.precision, L->variant, L->d.kin == ITSE_KIN_FDTD ? 1 : 0);
+        auto key = std::make_tuple(L->d.n, L->d.precision, L->variant,
+                                   (L->d.kin == ITSE_KIN_FDTD ? 1 : 0) | (L->host.cplx ? 2 : 0));
         if (!by.count(key)) order.push_back(key);
         by[key].push_back(L);
     }
@@ -156,7 +158,8 @@ extern "C" itse_status itse_batch_create(int count, itse_lattice *const *lats, v
         g.n = std::get<0>(key);
         g.prec = std::get<1>(key);
         g.variant = std::get<2>(key);
-        g.fdtd = std::get<3>(key) != 0;
+        g.fdtd = (std::get<3>(key) & 1) != 0;
+        g.cplx = (std::get<3>(key) & 2) != 0;
         g.jobs = dj;
         g.njobs = (int)jobs.size();
         g.lats = dl;

@@ -20,7 +20,10 @@ enum RowQ { RQ_PP = 0, RQ_PK, RQ_VPP, RQ_UU, RQ_X, RQ_Y, RQ_Z, RQ_R2, NQR };
 enum ColQ { CQ_NORM = 0, CQ_PAR, NQC };
 
 // Modes of the inverse (update) pass.
-enum InvMode { INV_UPDATE = 0, INV_EVAL = 1, INV_KOUT = 2 };
+// INV_KBUF: K psi_i written to L.kbuf + i N^3 (complex lattices).
+enum InvMode { INV_UPDATE = 0, INV_EVAL = 1, INV_KOUT = 2, INV_KBUF = 3 };
+// Reduction slots of the complex update kernel, per workgroup.
+enum CplxQ { XQ_VIPP = 0, XQ_UU, NQX };
 // Modes of the column pass.
 enum ColMode { COL_FWD = 0, COL_KIN = 2 };
 // Modes of the finalisation kernel.
@@ -29,7 +32,7 @@ enum FinMode { FIN_STEP = 0, FIN_EVAL = 1, FIN_NORM_ONLY = 2 };
 // Device-resident observables record (mirrors itse_obs).
 struct ObsDev {
     long long step;
-    double energy, kinetic, potential, norm2, x, y, z, r2, parity_even;
+    double energy, kinetic, potential, norm2, x, y, z, r2, parity_even, energy_imag;
 };
 
 // Everything the kernels need to know about one lattice.  Lives in device
@@ -49,6 +52,14 @@ struct LatDev {
     const void *tw;      // twiddle table exp(-2 pi i e / n), n entries, prec
     const double *ktab;  // per-axis kinetic term, n entries, FP64
     void *kout;          // output of H_K psi for the kinetic-only mode
+    // complex lattices (cplx = 1): states 0 and 1 hold Re psi and Im psi with
+    // coef[0][0] = coef[1][1], vi the imaginary part of the potential, kbuf
+    // 2 N^3 values receiving K Re psi and K Im psi
+    int cplx;
+    void *vi;
+    void *kbuf;
+    double *part_cplx;   // [nb_cplx][NQX]
+    int nb_cplx;
     // reduction arena
     double *part_rows;   // [MAXK][nb_rows][NQR]
     double *part_cols;   // [MAXK][nb_cols][NQC]
@@ -112,6 +123,9 @@ struct Launch {
     static hipError_t project_gram(int n, int kmax, const JobRef *lats, int nlats, int force, int which,
                                    hipStream_t s);
     static hipError_t combine(int n, const JobRef *jobs, int njobs, void *const *outs, hipStream_t s);
+    // complex lattices: the complex update after the transforms in mode INV_KBUF
+    // (mode INV_UPDATE or INV_EVAL); flat_blocks(n) workgroups per lattice
+    static hipError_t complex_update(int n, const JobRef *lats, int nlats, int mode, hipStream_t s);
     // H_K^(0) lattices: stencil, update and sums in one pass (modes of plane_inv)
     static hipError_t fdtd(int n, int kmax, int mode, const JobRef *jobs, int njobs, hipStream_t s);
     static int fdtd_blocks(int n);

@@ -304,6 +304,13 @@ hipError_t Launch<R>::combine(int n, const JobRef *jobs, int njobs, void *const 
 }
 
 template <typename R>
+hipError_t Launch<R>::complex_update(int n, const JobRef *lats, int nlats, int mode, hipStream_t s) {
+    if (nlats <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_complex_update<R>), dim3(flat_blocks(n), nlats), dim3(NT), 0, s, lats, mode);
+    return hipGetLastError();
+}
+
+template <typename R>
 hipError_t Launch<R>::convert_in(const void *src, int src_dtype, void *dst, size_t count, hipStream_t s) {
     const int blocks = (int)((count + NT - 1) / NT < 65536 ? (count + NT - 1) / NT : 65536);
     if (count == 0) return hipSuccess;

@@ -290,6 +290,12 @@ __device__ __forceinline__ void load_view(LatView<R, KM> &vw, const LatDev &L, i
     }
 }
 
+// Destination of K psi_i in the modes that write it.
+template <typename R>
+__device__ __forceinline__ R *kout_ptr(const LatDev &L, int mode, int i) {
+    return mode == INV_KBUF ? (R *)L.kbuf + (size_t)i * L.n * L.n * L.n : (R *)L.kout;
+}
+
 // Current state psi_i at flat offset off: sum_(j<=i) coef[j][i] u_j in FP64,
 // rounded once to the storage precision.
 template <typename R, int KM>
@@ -796,7 +802,8 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
 // ---------------------------------------------------------------------------
 // P3: inverse plane pass + update.  Sub-plane x * S + r and job from plane_block.
 // mode INV_UPDATE: u_i <- ((1 - h V) psi - dtau K psi) / (1 + h V)   (= A psi - B dtau K psi)
-// mode INV_EVAL: sums only; INV_KOUT: K psi written to L.kout.
+// mode INV_EVAL: sums only; INV_KOUT: K psi written to L.kout; INV_KBUF: K psi_i
+// written to L.kbuf + i N^3.
 // ---------------------------------------------------------------------------
 // MOM: position moments summed (the lattices' moments flag); without them the
 // update loop has the registers to take two chunks per load round.
@@ -861,7 +868,7 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     load_view(vw, L, i);
     const ITSE_GLOBAL R *v = gmem((const R *)L.v);
     ITSE_GLOBAL R *u = gmem((R *)state_buf(L, L.step, 1, i));
-    ITSE_GLOBAL R *kout = gmem((R *)L.kout);
+    ITSE_GLOBAL R *kout = gmem(kout_ptr<R>(L, mode, i));
     const R h = (R)L.h, dt = (R)L.dtau;
     const bool mom = MOM && L.moments != 0;
     const int center = L.center;
@@ -937,7 +944,7 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
             if (mode == INV_UPDATE) {
                 *(ITSE_GLOBAL Vec<R> *)(u + o0[t]) = un[0];
                 *(ITSE_GLOBAL Vec<R> *)(u + o1[t]) = un[1];
-            } else if (mode == INV_KOUT) {
+            } else if (mode >= INV_KOUT) {
                 *(ITSE_GLOBAL Vec<R> *)(kout + o0[t]) = kv[0];
                 *(ITSE_GLOBAL Vec<R> *)(kout + o1[t]) = kv[1];
             }
@@ -1023,7 +1030,7 @@ __global__ void __launch_bounds__(NT) k_fdtd(const JobRef *__restrict__ jobs, in
     load_view(vw, L, i);
     const ITSE_GLOBAL R *v = gmem((const R *)L.v);
     ITSE_GLOBAL R *u = gmem((R *)state_buf(L, L.step, 1, i));
-    ITSE_GLOBAL R *kout = gmem((R *)L.kout);
+    ITSE_GLOBAL R *kout = gmem(kout_ptr<R>(L, mode, i));
     const R h = (R)L.h, dt = (R)L.dtau;
     const R cK = (R)(1.0 / (2.0 * L.mass * L.a * L.a));
     const bool mom = L.moments != 0;
@@ -1095,7 +1102,7 @@ __global__ void __launch_bounds__(NT) k_fdtd(const JobRef *__restrict__ jobs, in
                 }
             }
             if (mode == INV_UPDATE) *(ITSE_GLOBAL Vec<R> *)(u + off(xx, y, z0)) = un;
-            else if (mode == INV_KOUT) *(ITSE_GLOBAL Vec<R> *)(kout + off(xx, y, z0)) = kv;
+            else if (mode >= INV_KOUT) *(ITSE_GLOBAL Vec<R> *)(kout + off(xx, y, z0)) = kv;
         }
         __syncthreads();
         pm = pc;
@@ -1443,6 +1450,85 @@ __global__ void __launch_bounds__(NT) k_combine(const JobRef *__restrict__ jobs,
     R *out = (R *)outs[blockIdx.y];
     for (size_t s = (size_t)blockIdx.x * NT + threadIdx.x; s < n3; s += (size_t)gridDim.x * NT)
         out[s] = lazy_psi(vw, s);
+}
+
+// ---------------------------------------------------------------------------
+// Complex update (complex lattices; runs after the transform passes in mode
+// INV_KBUF have written K Re psi and K Im psi to kbuf).  With psi = Re + i Im,
+// Re = c u_0, Im = c u_1 (c = coef[0][0] = coef[1][1], the FP64 product rounded
+// once as in the passes), V = Vr + i Vi and h = dtau / 2, the map of equation
+// iter_proced with complex A and B:
+//   psi' = A psi - B dtau K psi = ((1 - h V) psi - dtau K psi) / (1 + h V),
+// written to the raw arrays of the next step.  FP64 partial sums per workgroup:
+// sum Vi |psi|^2 and sum |psi'|^2 (mode INV_EVAL: sums only).  Grid
+// (nb_cplx, lattices); each thread takes two 16-byte vectors per round in a
+// stride over the lattice (all loads of a round issued before use).
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(NT) k_complex_update(const JobRef *__restrict__ lats, int mode) {
+    constexpr int VL = VLEN<R>;
+    constexpr int U = 2;
+    __shared__ double red[NQX * (NT / 64)];
+    const LatDev &L = *lats[blockIdx.y].lat;
+    const size_t n3 = (size_t)L.n * L.n * L.n;
+    const size_t nv = n3 / VL;
+    const double c = L.coef[0][0];
+    const ITSE_GLOBAL R *u0 = gmem((const R *)state_buf(L, L.step, 0, 0));
+    const ITSE_GLOBAL R *u1 = gmem((const R *)state_buf(L, L.step, 0, 1));
+    ITSE_GLOBAL R *w0 = gmem((R *)state_buf(L, L.step, 1, 0));
+    ITSE_GLOBAL R *w1 = gmem((R *)state_buf(L, L.step, 1, 1));
+    const ITSE_GLOBAL R *kr = gmem((const R *)L.kbuf);
+    const ITSE_GLOBAL R *ki = kr + n3;
+    const ITSE_GLOBAL R *vr = gmem((const R *)L.v);
+    const ITSE_GLOBAL R *vi = gmem((const R *)L.vi);
+    const R h = (R)L.h, dt = (R)L.dtau;
+    const size_t stride = (size_t)gridDim.x * NT;
+    double acc[NQX] = {0.0, 0.0};
+    for (size_t q0 = (size_t)blockIdx.x * NT + threadIdx.x; q0 < nv; q0 += U * stride) {
+        Vec<R> a0[U], a1[U], k0[U], k1[U], p0[U], p1[U];
+        bool ok[U];
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const size_t q = q0 + t * stride;
+            ok[t] = q < nv;
+            if (ok[t]) {
+                const size_t o = q * VL;
+                a0[t] = *(const ITSE_GLOBAL Vec<R> *)(u0 + o);
+                a1[t] = *(const ITSE_GLOBAL Vec<R> *)(u1 + o);
+                k0[t] = *(const ITSE_GLOBAL Vec<R> *)(kr + o);
+                k1[t] = *(const ITSE_GLOBAL Vec<R> *)(ki + o);
+                p0[t] = *(const ITSE_GLOBAL Vec<R> *)(vr + o);
+                p1[t] = *(const ITSE_GLOBAL Vec<R> *)(vi + o);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            if (!ok[t]) continue;
+            Vec<R> n0, n1;
+#pragma unroll
+            for (int k = 0; k < VL; ++k) {
+                const R pr = (R)(c * (double)a0[t][k]), pi = (R)(c * (double)a1[t][k]);
+                const R hr = h * p0[t][k], hi = h * p1[t][k];
+                // numerator (1 - h V) psi - dtau K psi, denominator d = 1 + h V
+                const R nr = pr * ((R)1 - hr) + hi * pi - dt * k0[t][k];
+                const R ni = pi * ((R)1 - hr) - hi * pr - dt * k1[t][k];
+                const R dr = (R)1 + hr;
+                const R inv = div_fast<R>((R)1, dr * dr + hi * hi);
+                const R ur = (nr * dr + ni * hi) * inv, ui = (ni * dr - nr * hi) * inv;
+                n0[k] = ur;
+                n1[k] = ui;
+                const double m2 = (double)pr * (double)pr + (double)pi * (double)pi;
+                acc[XQ_VIPP] += (double)p1[t][k] * m2;
+                acc[XQ_UU] += (double)ur * (double)ur + (double)ui * (double)ui;
+            }
+            if (mode == INV_UPDATE) {
+                const size_t o = (q0 + t * stride) * VL;
+                *(ITSE_GLOBAL Vec<R> *)(w0 + o) = n0;
+                *(ITSE_GLOBAL Vec<R> *)(w1 + o) = n1;
+            }
+        }
+    }
+    block_sums<NQX, NT>(acc, L.part_cplx + (size_t)blockIdx.x * NQX, red);
 }
 
 // ---------------------------------------------------------------------------

@@ -28,6 +28,7 @@ struct Group {
     int kmax = 1;                  // largest number of states among the lattices
     int needs = NEED_PROJECT | NEED_GRAM | NEED_MOMENTS;  // optional work of a step
     bool fdtd = false;             // H_K^(0): one stencil pass instead of the transforms
+    bool cplx = false;             // complex lattices: transforms to kbuf, complex update
 };
 
 itse_status fail(itse_status st, const char *fmt, ...);

@@ -60,23 +60,29 @@ constexpr int FIN_NT = 512;
 constexpr int FIN_QMAX = MAXK * (NQR + NQC) + MAXK * (MAXK + 1) / 2;
 
 // Which sums a finalisation forms: K * NQR row sums, K * NQC column sums (when
-// moments are on) and, when Gram sums exist, the K (K + 1) / 2 Gram entries.  Gram
-// sums of the updated (and projected) arrays exist on orthogonalisation steps and
-// whenever states are projected (their diagonal then gives the norms).
+// moments are on), when Gram sums exist the K (K + 1) / 2 Gram entries, and for
+// complex lattices the NQX sums of the complex update.  Gram sums of the updated
+// (and projected) arrays exist on orthogonalisation steps and whenever states are
+// projected (their diagonal then gives the norms).  A complex lattice (K = 2: the
+// real and imaginary parts) is never orthogonalised.
 struct FinLayout {
     bool ortho_step, have_gram;
-    int q_rows, q_cols, q_gram, total;
+    int q_rows, q_cols, q_gram, q_cplx, total;
 };
 
 __device__ __forceinline__ FinLayout fin_layout(const LatDev &L, int mode) {
     FinLayout f;
     const int K = L.nstates;
-    f.ortho_step = (mode == FIN_STEP) && K > 1 && L.ortho_every > 0 && ((L.step + 1) % L.ortho_every) == 0;
+    f.ortho_step = (mode == FIN_STEP) && !L.cplx && K > 1 && L.ortho_every > 0 &&
+                   ((L.step + 1) % L.ortho_every) == 0;
     f.have_gram = (mode == FIN_STEP) && (f.ortho_step || L.proj_mode != 0);
     f.q_rows = K * NQR;
-    f.q_cols = L.moments ? K * NQC : 0;
+    // the parity weight comes from the column pass (Parseval), which H_K^(0)
+    // lattices do not run
+    f.q_cols = (L.moments && L.kin != ITSE_KIN_FDTD) ? K * NQC : 0;
     f.q_gram = f.have_gram ? K * (K + 1) / 2 : 0;
-    f.total = f.q_rows + f.q_cols + f.q_gram;
+    f.q_cplx = L.cplx ? NQX : 0;
+    f.total = f.q_rows + f.q_cols + f.q_gram + f.q_cplx;
     return f;
 }
 
@@ -102,11 +108,15 @@ __global__ void __launch_bounds__(FIN_NT) k_fin_sums(const JobRef *__restrict__ 
         p = L.part_cols + (size_t)i * L.nb_cols * NQC + c;
         count = L.nb_cols;
         stride = NQC;
-    } else {
+    } else if (q < f.q_rows + f.q_cols + f.q_gram) {
         const int slot = q - f.q_rows - f.q_cols;  // l (l + 1) / 2 + j
         p = L.part_gram + slot;
         count = L.nb_gram;
         stride = NG;
+    } else {
+        p = L.part_cplx + (q - f.q_rows - f.q_cols - f.q_gram);
+        count = L.nb_cplx;
+        stride = NQX;
     }
     // up to 8 loads in flight per thread, added in a fixed order
     double acc[1] = {0.0};
@@ -141,7 +151,16 @@ __global__ void __launch_bounds__(64) k_fin_tail(const JobRef *__restrict__ lats
     for (int t = lane; t < f.total; t += 64) sums[t] = L.fin_sums[t];
     __syncthreads();
     int err = 0;
-    if (lane < K) {
+    // a complex lattice: one observable record from the sums of both parts
+    const int nobs = L.cplx ? 1 : K;
+    if (L.cplx && lane == 0) {
+        for (int c = 0; c < NQR; ++c) sums[c] += sums[NQR + c];
+        if (f.q_cols)
+            for (int c = 0; c < NQC; ++c) sums[f.q_rows + c] += sums[f.q_rows + NQC + c];
+    }
+    __syncthreads();
+    const double *xs = sums + f.q_rows + f.q_cols + f.q_gram;  // complex-update sums
+    if (lane < nobs) {
         const double *rows = sums + lane * NQR;
         const double *cols = sums + f.q_rows + lane * NQC;
         ObsDev o;
@@ -156,12 +175,13 @@ __global__ void __launch_bounds__(64) k_fin_tail(const JobRef *__restrict__ lats
             o.y = rows[RQ_Y] / pp;
             o.z = rows[RQ_Z] / pp;
             o.r2 = rows[RQ_R2] / pp;
-            o.parity_even = 0.5 * (1.0 + cols[CQ_PAR] / cols[CQ_NORM]);
+            o.parity_even = f.q_cols ? 0.5 * (1.0 + cols[CQ_PAR] / cols[CQ_NORM]) : -1.0;
         } else {
             o.x = o.y = o.z = o.r2 = 0.0;
             o.parity_even = -1.0;
         }
-        if (!isfinite(o.energy) || !isfinite(pp) || pp <= 0.0) err |= 1;
+        o.energy_imag = L.cplx ? xs[XQ_VIPP] / pp : 0.0;
+        if (!isfinite(o.energy) || !isfinite(o.energy_imag) || !isfinite(pp) || pp <= 0.0) err |= 1;
         L.obs[lane] = o;
         if (mode == FIN_STEP && L.hist) L.hist[(size_t)(L.step % HIST_CAP) * MAXK + lane] = o;
     }
@@ -201,7 +221,12 @@ __global__ void __launch_bounds__(64) k_fin_tail(const JobRef *__restrict__ lats
                 err |= 2;
             }
         }
-        if (!done) {
+        if (!done && L.cplx) {
+            // |psi'|^2 summed over both parts; one coefficient for both
+            const double nn = f.have_gram ? gram[0] + gram[2] : xs[XQ_UU];
+            if (!(nn > 0.0) || !isfinite(nn)) err |= 1;
+            M[0][0] = M[1][1] = 1.0 / sqrt(nn);
+        } else if (!done) {
             for (int i = 0; i < K; ++i) {
                 const double nn = f.have_gram ? gram[i * (i + 1) / 2 + i] : sums[i * NQR + RQ_UU];
                 if (!(nn > 0.0) || !isfinite(nn)) err |= 1;
@@ -364,6 +389,16 @@ int step_needs(const LatDev &o, int nstates) {
 template <typename R>
 static hipError_t seq_step(const Group &g, hipStream_t s) {
     hipError_t e;
+    if (g.cplx) {
+        // complex lattices: K Re psi, K Im psi to kbuf, then the complex update;
+        // projection (both parts, same sign and axes) with the norm in the Gram pass
+        if ((e = seq_forward_kin<R>(g, INV_KBUF, s)) != hipSuccess) return e;
+        if ((e = Launch<R>::complex_update(g.n, g.lats, g.nlats, INV_UPDATE, s)) != hipSuccess) return e;
+        if ((g.needs & NEED_GRAM) &&
+            (e = Launch<R>::project_gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s)) != hipSuccess)
+            return e;
+        return launch_finalize(g.lats, g.nlats, FIN_STEP, s);
+    }
     if ((e = seq_forward_kin<R>(g, INV_UPDATE, s)) != hipSuccess) return e;
     if ((g.needs & NEED_PROJECT) && (e = Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, 1, s)) != hipSuccess)
         return e;
@@ -378,8 +413,11 @@ hipError_t enqueue_step(const Group &g, hipStream_t s) {
 }
 
 hipError_t enqueue_eval(const Group &g, hipStream_t s) {
-    hipError_t e = g.prec == ITSE_FP32 ? seq_forward_kin<float>(g, INV_EVAL, s)
-                                       : seq_forward_kin<double>(g, INV_EVAL, s);
+    const int mode = g.cplx ? INV_KBUF : INV_EVAL;
+    hipError_t e = g.prec == ITSE_FP32 ? seq_forward_kin<float>(g, mode, s) : seq_forward_kin<double>(g, mode, s);
+    if (e == hipSuccess && g.cplx)
+        e = g.prec == ITSE_FP32 ? Launch<float>::complex_update(g.n, g.lats, g.nlats, INV_EVAL, s)
+                                : Launch<double>::complex_update(g.n, g.lats, g.nlats, INV_EVAL, s);
     if (e != hipSuccess) return e;
     return launch_finalize(g.lats, g.nlats, FIN_EVAL, s);
 }
@@ -468,6 +506,7 @@ Group single_group(itse_lattice *L) {
     g.kmax = L->d.nstates;
     g.needs = step_needs(L->host, L->d.nstates);
     g.fdtd = L->d.kin == ITSE_KIN_FDTD;
+    g.cplx = L->host.cplx != 0;
     return g;
 }
 
@@ -500,7 +539,8 @@ extern "C" size_t itse_footprint_bytes(const itse_desc *d) {
     if (!d || d->n < 1) return 0;
     const size_t w = real_bytes(d->precision);
     const size_t n = (size_t)d->n, n3 = n * n * n;
-    const size_t K = (size_t)std::max(1, std::min(d->nstates, MAXK));
+    const bool cplx = d->complex_psi == 1;
+    const size_t K = cplx ? 2 : (size_t)std::max(1, std::min(d->nstates, MAXK));
     const size_t spec = spec_bytes(d->n, d->precision);
     size_t arena = 0;
     if (prec_supported(d->n, d->precision)) {
@@ -518,7 +558,9 @@ extern "C" size_t itse_footprint_bytes(const itse_desc *d) {
     const size_t hist = (size_t)HIST_CAP * MAXK * sizeof(ObsDev);
     // per state: two raw arrays u_i (current, next) and the half spectrum; shared: potential, scratch array,
     // staging for a host upload in the other precision (n^3 doubles), partial sums, history
-    return K * (2 * n3 * w + spec) + n3 * w + n3 * w + n3 * 8 + arena + hist + sizeof(LatDev) + 8192 + n * 8;
+    // complex lattices also: Im V, K Re psi and K Im psi, the complex-update partials
+    const size_t cx = cplx ? 3 * n3 * w + (size_t)flat_blocks(d->n) * NQX * 8 : 0;
+    return K * (2 * n3 * w + spec) + n3 * w + n3 * w + n3 * 8 + arena + hist + sizeof(LatDev) + 8192 + n * 8 + cx;
 }
 
 static bool valid_n(int n) {
@@ -541,6 +583,8 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
     if (d->precision != ITSE_FP32 && d->precision != ITSE_FP64) return fail(ITSE_EINVAL, "precision");
     if (d->center != ITSE_CENTER_CELL && d->center != ITSE_CENTER_ORIGIN) return fail(ITSE_EINVAL, "center");
     if (d->nstates < 1 || d->nstates > MAXK) return fail(ITSE_EINVAL, "nstates = %d (1..%d)", d->nstates, MAXK);
+    if (d->complex_psi != 0 && d->complex_psi != 1) return fail(ITSE_EINVAL, "complex_psi = %d", d->complex_psi);
+    if (d->complex_psi && d->nstates != 1) return fail(ITSE_EINVAL, "complex_psi needs nstates = 1");
     if (!prec_supported(d->n, d->precision)) return fail(ITSE_EINVAL, "n = %d not built", d->n);
     const double tmax = max_symbol(*d);
     if (d->dtau * tmax > 1.95)
@@ -549,16 +593,17 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
 
     itse_lattice *L = new itse_lattice();
     L->d = *d;
+    if (d->complex_psi) L->d.nstates = 2;  // Re psi and Im psi
     L->stream = (hipStream_t)hip_stream;
     L->alloc = alloc;
     L->freefn = free_fn;
     L->alloc_user = alloc_user;
-    L->variant = schedule_variant_for(d->n, d->precision, d->nstates);
+    L->variant = schedule_variant_for(d->n, d->precision, L->d.nstates);
     L->sched = prec_schedule(d->n, d->precision, L->variant);
     if (d->kin == ITSE_KIN_FDTD)
         L->sched.nb_rows = d->precision == ITSE_FP32 ? Launch<float>::fdtd_blocks(d->n)
                                                      : Launch<double>::fdtd_blocks(d->n);
-    const int n = d->n, K = d->nstates;
+    const int n = d->n, K = L->d.nstates;
     const size_t w = real_bytes(d->precision);
     const size_t n3 = (size_t)n * n * n;
     const size_t spec = spec_bytes(n, d->precision);
@@ -597,6 +642,14 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
     H.part_proj = (double *)lat_alloc(L, (size_t)MAXK * H.nb_proj * 8);
     H.part_gram = (double *)lat_alloc(L, (size_t)H.nb_gram * (MAXK * (MAXK + 1) / 2) * 8);
     H.hist = (ObsDev *)lat_alloc(L, (size_t)HIST_CAP * MAXK * sizeof(ObsDev));
+    if (d->complex_psi) {
+        H.cplx = 1;
+        H.nb_cplx = flat_blocks(n);
+        H.vi = lat_alloc(L, n3 * w);
+        H.kbuf = lat_alloc(L, 2 * n3 * w);
+        H.part_cplx = (double *)lat_alloc(L, (size_t)H.nb_cplx * NQX * 8);
+        if (!H.vi || !H.kbuf || !H.part_cplx) return cleanup(fail(ITSE_ENOMEM, "complex-state buffers"));
+    }
     double *ktab = (double *)lat_alloc(L, (size_t)n * 8);
     L->dev = (LatDev *)lat_alloc(L, sizeof(LatDev));
     L->jobs_dev = (JobRef *)lat_alloc(L, sizeof(JobRef) * MAXK);
@@ -653,6 +706,7 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
         CK(hipMemsetAsync(H.ub[1][i], 0, n3 * w, s));
     }
     CK(hipMemsetAsync(H.v, 0, n3 * w, s));
+    if (H.vi) CK(hipMemsetAsync(H.vi, 0, n3 * w, s));
     CK(hipMemsetAsync(H.hist, 0, (size_t)HIST_CAP * MAXK * sizeof(ObsDev), s));
     CK(hipMemcpyAsync(L->dev, &H, sizeof(LatDev), hipMemcpyHostToDevice, s));
     CK(hipStreamSynchronize(s));
@@ -740,6 +794,19 @@ extern "C" itse_status itse_set_potential(itse_lattice *L, const void *v, int dt
     return ITSE_OK;
 }
 
+extern "C" itse_status itse_set_potential_imag(itse_lattice *L, const void *v, int dtype, int on_device) {
+    if (!L || !v) return fail(ITSE_EINVAL, "null argument");
+    if (!L->host.cplx) return fail(ITSE_ESTATE, "imaginary potential on a lattice of real states");
+    if (dtype != ITSE_DTYPE_F32 && dtype != ITSE_DTYPE_F64) return fail(ITSE_EINVAL, "dtype");
+    const size_t n3 = (size_t)L->d.n * L->d.n * L->d.n;
+    if (!on_device)
+        for (size_t s = 0; s < n3; ++s) {
+            const double x = dtype == ITSE_DTYPE_F32 ? (double)((const float *)v)[s] : ((const double *)v)[s];
+            if (!std::isfinite(x)) return fail(ITSE_ENONFINITE, "Im V has a non-finite value at site %zu", s);
+        }
+    return copy_in(L, v, dtype, on_device, L->host.vi);
+}
+
 extern "C" itse_status itse_set_state(itse_lattice *L, int i, const void *psi, int dtype, int on_device) {
     if (!L || !psi) return fail(ITSE_EINVAL, "null argument");
     if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
@@ -785,10 +852,19 @@ extern "C" itse_status itse_set_step_opts(itse_lattice *L, const itse_step_opts 
     L->opts = *o;
     L->host.ortho_every = o->ortho_every;
     L->host.moments = o->moments ? 1 : 0;
+    // a complex lattice: never orthogonalised; parity[0] / axes[0] project both parts
+    itse_step_opts eff = *o;
+    if (L->host.cplx) {
+        L->host.ortho_every = 0;
+        for (int i = 1; i < MAXK; ++i) {
+            eff.parity[i] = i == 1 ? o->parity[0] : 0;
+            eff.axes[i] = i == 1 ? o->axes[0] : 7;
+        }
+    }
     int mode = 0, paxes = 0;
     for (int i = 0; i < MAXK; ++i) {
-        L->host.psign[i] = i < L->d.nstates ? o->parity[i] : 0;
-        L->host.paxes[i] = o->parity[i] ? o->axes[i] : 7;
+        L->host.psign[i] = i < L->d.nstates ? eff.parity[i] : 0;
+        L->host.paxes[i] = eff.parity[i] ? eff.axes[i] : 7;
         if (L->host.psign[i] != 0) {
             if (mode == 0) {
                 mode = 1;
@@ -912,7 +988,7 @@ extern "C" itse_status itse_evaluate(itse_lattice *L, int moments) {
 
 extern "C" itse_status itse_observe(itse_lattice *L, int i, itse_obs *out) {
     if (!L || !out) return fail(ITSE_EINVAL, "null argument");
-    if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
+    if (i < 0 || i >= (L->host.cplx ? 1 : L->d.nstates)) return fail(ITSE_EINVAL, "state index %d", i);
     ObsDev o;
     HIPCHK(hipMemcpyAsync(&o, (char *)L->dev + offsetof(LatDev, obs) + i * sizeof(ObsDev), sizeof(ObsDev),
                           hipMemcpyDeviceToHost, L->stream));
@@ -926,7 +1002,7 @@ extern "C" itse_status itse_history(itse_lattice *L, int count, itse_obs *out) {
     if (!L || (!out && count > 0)) return fail(ITSE_EINVAL, "null argument");
     if (count < 0 || count > HIST_CAP || count > L->steps_host)
         return fail(ITSE_EINVAL, "count %d (steps taken %lld, capacity %d)", count, L->steps_host, HIST_CAP);
-    const int K = L->d.nstates;
+    const int K = L->host.cplx ? 1 : L->d.nstates;  // records per step
     std::vector<ObsDev> all((size_t)HIST_CAP * MAXK);
     HIPCHK(hipMemcpyAsync(all.data(), L->host.hist, all.size() * sizeof(ObsDev), hipMemcpyDeviceToHost, L->stream));
     itse_status st = check_device_error(L);
@@ -977,6 +1053,7 @@ static itse_status gram_host(itse_lattice *L, double G[MAXK][MAXK]) {
 }  // namespace itse
 
 extern "C" itse_status itse_orthogonalise(itse_lattice *L, int i) {
+    if (L && L->host.cplx) return fail(ITSE_ESTATE, "%s: real states only", "itse_orthogonalise");
     if (!L) return fail(ITSE_EINVAL, "null lattice");
     if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
     itse_status st = materialise(L);
@@ -1034,6 +1111,7 @@ itse_status norm_host(itse_lattice *L, int i, double *out) {
 }  // namespace itse
 
 extern "C" itse_status itse_project_parity(itse_lattice *L, int i, int sign, int axes, double *weight) {
+    if (L && L->host.cplx) return fail(ITSE_ESTATE, "%s: real states only", "itse_project_parity");
     if (!L) return fail(ITSE_EINVAL, "null lattice");
     if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
     if (sign != 1 && sign != -1) return fail(ITSE_EINVAL, "sign must be +1 or -1");
@@ -1088,6 +1166,7 @@ extern "C" itse_status itse_spectrum(itse_lattice *L, int i, void *out) {
 }
 
 extern "C" itse_status itse_polish(itse_lattice *L, int i, itse_obs *out) {
+    if (L && L->host.cplx) return fail(ITSE_ESTATE, "%s: real states only", "itse_polish");
     if (!L || !out) return fail(ITSE_EINVAL, "null argument");
     if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
     if (L->d.precision == ITSE_FP64) {
@@ -1128,6 +1207,7 @@ static double *ana_scratch(itse_lattice *L, size_t doubles) {
 }
 
 extern "C" itse_status itse_analyse(itse_lattice *L, int i, double min_sep_edge, itse_analysis *out) {
+    if (L && L->host.cplx) return fail(ITSE_ESTATE, "%s: real states only", "itse_analyse");
     if (!L || !out) return fail(ITSE_EINVAL, "null argument");
     if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
     if (!(min_sep_edge >= 0.0 && min_sep_edge < 1.0)) return fail(ITSE_EINVAL, "min_sep_edge = %g", min_sep_edge);
@@ -1156,6 +1236,7 @@ extern "C" itse_status itse_analyse(itse_lattice *L, int i, double min_sep_edge,
 
 extern "C" itse_status itse_momentum_radial(itse_lattice *L, int i, int nbins, double *count, double *p, double *psi,
                                             double *y) {
+    if (L && L->host.cplx) return fail(ITSE_ESTATE, "itse_momentum_radial: real states only");
     if (!L) return fail(ITSE_EINVAL, "null lattice");
     if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
     if (nbins < 1 || nbins > MOM_MAXBINS) return fail(ITSE_EINVAL, "nbins = %d (1..%d)", nbins, MOM_MAXBINS);
@@ -1198,6 +1279,7 @@ extern "C" itse_status itse_momentum_radial(itse_lattice *L, int i, int nbins, d
 // Snapshot-overlap extraction of excited states (section "The iterative procedure")
 // ------------------------------------------------------------------------------------
 extern "C" itse_status itse_snapshot_push(itse_lattice *L) {
+    if (L && L->host.cplx) return fail(ITSE_ESTATE, "%s: real states only", "itse_snapshot_push");
     if (!L) return fail(ITSE_EINVAL, "null lattice");
     const size_t n3 = (size_t)L->d.n * L->d.n * L->d.n;
     if (!L->snap[0]) {
@@ -1237,6 +1319,7 @@ extern "C" itse_status itse_snapshot_clear(itse_lattice *L) {
 
 extern "C" itse_status itse_snapshot_extract(itse_lattice *L, itse_obs *out, int *n_out, void *states_out, int dtype,
                                              int on_device) {
+    if (L && L->host.cplx) return fail(ITSE_ESTATE, "itse_snapshot_extract: real states only");
     if (!L || !out || !n_out) return fail(ITSE_EINVAL, "null argument");
     if (states_out && dtype != ITSE_DTYPE_F32 && dtype != ITSE_DTYPE_F64) return fail(ITSE_EINVAL, "dtype");
     const int ne = 1 + L->snap_count;
@@ -1292,11 +1375,16 @@ static hipError_t launch_pass(const Group &g, int p, hipStream_t s) {
     switch (p) {
     case 0: return Launch<R>::plane_fwd(g.n, g.variant, g.kmax, g.jobs, g.njobs, s);
     case 1: return Launch<R>::columns(g.n, g.variant, COL_KIN, 1, g.jobs, g.njobs, nullptr, s);
-    case 2:
-        return g.fdtd ? Launch<R>::fdtd(g.n, g.kmax, INV_UPDATE, g.jobs, g.njobs, s)
-                      : Launch<R>::plane_inv(g.n, g.variant, INV_UPDATE, (g.needs & NEED_MOMENTS) ? 1 : 0, g.kmax,
+    case 2: {
+        const int mode = g.cplx ? INV_KBUF : INV_UPDATE;
+        return g.fdtd ? Launch<R>::fdtd(g.n, g.kmax, mode, g.jobs, g.njobs, s)
+                      : Launch<R>::plane_inv(g.n, g.variant, mode, (g.needs & NEED_MOMENTS) ? 1 : 0, g.kmax,
                                              g.jobs, g.njobs, s);
-    case 3: return (g.needs & NEED_PROJECT) ? Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, 1, s) : hipSuccess;
+    }
+    case 3:
+        // complex lattices: the complex update takes the slot of the per-state projection
+        if (g.cplx) return Launch<R>::complex_update(g.n, g.lats, g.nlats, INV_UPDATE, s);
+        return (g.needs & NEED_PROJECT) ? Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, 1, s) : hipSuccess;
     case 4:
         return (g.needs & NEED_GRAM) ? Launch<R>::project_gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s) : hipSuccess;
     default: return launch_finalize(g.lats, g.nlats, FIN_STEP, s);
@@ -1315,7 +1403,7 @@ extern "C" itse_status itse_profile_step(itse_lattice *L, int nsteps, double *ms
     // passes a step of these options does not launch are reported as 0
     bool launched[NPASS];
     for (int p = 0; p < NPASS; ++p)
-        launched[p] = !((p == 3 && !(g.needs & NEED_PROJECT)) || (p == 4 && !(g.needs & NEED_GRAM)) ||
+        launched[p] = !((p == 3 && !(g.needs & NEED_PROJECT) && !g.cplx) || (p == 4 && !(g.needs & NEED_GRAM)) ||
                         (p < 2 && g.fdtd));
     std::vector<hipEvent_t> ev((size_t)nsteps * (NPASS + 1));
     for (auto &e : ev) HIPCHK(hipEventCreate(&e));
@@ -1351,7 +1439,8 @@ extern "C" itse_status itse_profile_step(itse_lattice *L, int nsteps, double *ms
     if (names && names_len) {
         std::string js = "[";
         for (int p = 0; p < NPASS; ++p)
-            js += std::string(p ? ", " : "") + "\"" + (p == 2 && g.fdtd ? "k_fdtd" : pass_names[p]) + "\"";
+            js += std::string(p ? ", " : "") + "\"" +
+                  (p == 2 && g.fdtd ? "k_fdtd" : p == 3 && g.cplx ? "k_complex_update" : pass_names[p]) + "\"";
         js += "]";
         snprintf(names, names_len, "%s", js.c_str());
     }

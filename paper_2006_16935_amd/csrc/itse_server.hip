@@ -128,6 +128,7 @@ extern "C" itse_status itse_server_submit(itse_server *s, const itse_request *re
     if (!s || !req || !req->potential || !req->states) return fail(ITSE_EINVAL, "null argument");
     const itse_desc &d = req->desc;
     if (d.nstates < 1 || d.nstates > ITSE_MAX_STATES) return fail(ITSE_EINVAL, "nstates = %d", d.nstates);
+    if (d.complex_psi) return fail(ITSE_EINVAL, "the server takes real states only (complex_psi = 0)");
     if ((req->potential_dtype != ITSE_DTYPE_F32 && req->potential_dtype != ITSE_DTYPE_F64) ||
         (req->state_dtype != ITSE_DTYPE_F32 && req->state_dtype != ITSE_DTYPE_F64))
         return fail(ITSE_EINVAL, "dtype");

@@ -88,17 +88,22 @@ def make_opts(nstates: int, ortho_every: int = 1, moments: bool = False,
 
 
 class Lattice:
-    """One N^3 lattice with `nstates` states evolved by the imaginary-time map."""
+    """One N^3 lattice with `nstates` states evolved by the imaginary-time map.
+
+    complex_psi=True: one complex state in a complex potential (set_potential takes
+    a complex array; set_state(0, psi) / get_state(0) complex arrays; the library
+    holds Re psi and Im psi as its states 0 and 1)."""
 
     def __init__(self, n: int, a: float, mass: float, dtau: float, kin: int = _lib.KIN_REL_LAT,
                  subtract_rest_mass: bool = True, precision: str = "fp64", center: str = "origin",
-                 nstates: int = 1, stream=None, torch_memory: bool = True):
+                 nstates: int = 1, stream=None, torch_memory: bool = True, complex_psi: bool = False):
         self._L = _lib.load()
         self.n, self.nstates = int(n), int(nstates)
+        self.complex_psi = bool(complex_psi)
         self.precision = precision
         self.desc = _lib.Desc(int(n), float(a), float(mass), float(dtau), int(kin),
                               1 if subtract_rest_mass else 0, _PREC[precision], _CENTER[center],
-                              int(nstates))
+                              int(nstates), 1 if complex_psi else 0)
         self._stream_ptr, self.stream = _stream_handle(stream)
         self._alloc = _TorchAllocator() if torch_memory else None
         handle = ctypes.c_void_p()
@@ -144,17 +149,53 @@ class Lattice:
         assert a.size == self.n ** 3, "expected N^3 values"
         return a.ctypes.data_as(ctypes.c_void_p), _dtype_code(a), 0, a
 
+    @staticmethod
+    def _parts(x):
+        """Real and imaginary parts of a complex array or tensor (contiguous copies)."""
+        if _is_device_tensor(x):
+            return x.real.contiguous(), x.imag.contiguous()
+        x = np.asarray(x)
+        return np.ascontiguousarray(x.real), np.ascontiguousarray(x.imag)
+
     def set_potential(self, v):
+        if self.complex_psi:
+            vr, vi = self._parts(v)
+            p, dt, dev, keep = self._in(vr)
+            check(self._L.itse_set_potential(self.h, p, dt, dev))
+            self.set_potential_imag(vi)
+            return
         p, dt, dev, keep = self._in(v)
         check(self._L.itse_set_potential(self.h, p, dt, dev))
 
+    def set_potential_imag(self, vi):
+        """Imaginary part of the potential (complex lattices only)."""
+        p, dt, dev, keep = self._in(vi)
+        check(self._L.itse_set_potential_imag(self.h, p, dt, dev))
+        if dev:
+            self.sync()
+
     def set_state(self, i: int, psi):
+        if self.complex_psi and int(i) == 0:
+            re, im = self._parts(psi)
+            for part, arr in ((0, re), (1, im)):
+                p, dt, dev, keep = self._in(arr)
+                check(self._L.itse_set_state(self.h, part, p, dt, dev))
+                if dev:
+                    self.sync()
+            return
         p, dt, dev, keep = self._in(psi)
         check(self._L.itse_set_state(self.h, int(i), p, dt, dev))
         if dev:
             self.sync()
 
     def get_state(self, i: int, dtype=np.float64, device: bool = False):
+        if self.complex_psi and int(i) == 0:
+            re = self._get_part(0, dtype, device)
+            im = self._get_part(1, dtype, device)
+            return re + 1j * im if not device else _torch().complex(re, im)
+        return self._get_part(i, dtype, device)
+
+    def _get_part(self, i: int, dtype=np.float64, device: bool = False):
         n = self.n
         if device:
             torch = _torch()

@@ -69,6 +69,19 @@ def potential_harmonic(n: int, a: float, center: str = CELL, coef: float = 0.5) 
     return coef * r * r
 
 
+def potential_harmonic_complex(n: int, a: float, center: str = CELL, coef: float = 0.5,
+                               imag: float = 1.0) -> np.ndarray:
+    """V = coef * (1 + i imag) r^2: with imag = 1 the paper's complex 3d harmonic
+    oscillator shape (hard-coded potential 5) with a positive real part."""
+    _, _, _, r = radius_grid(n, a, center)
+    return coef * (1.0 + 1j * imag) * r * r
+
+
+def random_state_complex(n: int, seed: int, dtype=np.complex128) -> np.ndarray:
+    """Real part from ``default_rng(seed)``, imaginary part from ``default_rng(seed + 1)``."""
+    return (random_state(n, seed) + 1j * random_state(n, seed + 1)).astype(dtype, copy=False)
+
+
 def potential_cornell(n: int, a: float, center: str = ORIGIN, sigma: float = 0.2,
                       alpha: float = 0.4, reg: Optional[float] = None,
                       aniso: float = 0.0) -> np.ndarray:

@@ -35,13 +35,18 @@ def test_version_and_footprint():
     # states + current states + spectra + potential at least
     assert fp > 3 * (2 * n3 * 4 + 256 * 256 * 129 * 8) + n3 * 4
     assert fp < 2 * 1024 ** 3
+    # a complex state: Re and Im arrays, their spectra, Im V and K psi for both parts
+    dc = _lib.Desc(256, 0.025, 1.3, 0.00625, 3, 1, _lib.FP32, 1, 1, 1)
+    d2 = _lib.Desc(256, 0.025, 1.3, 0.00625, 3, 1, _lib.FP32, 1, 2)
+    fc, f2 = L.itse_footprint_bytes(ctypes.byref(dc)), L.itse_footprint_bytes(ctypes.byref(d2))
+    assert fc - f2 >= 3 * n3 * 4
 
 
 def _create(**kw):
     from paper_2006_16935_amd import _lib
     L = _lib.load()
     base = dict(n=32, a=0.1, mass=1.0, dtau=0.00125, kin=1, subtract_rest_mass=1,
-                precision=_lib.FP64, center=0, nstates=1)
+                precision=_lib.FP64, center=0, nstates=1, complex_psi=0)
     base.update(kw)
     d = _lib.Desc(*[base[k] for k, _ in _lib.Desc._fields_])
     h = ctypes.c_void_p()
@@ -61,6 +66,8 @@ def _create(**kw):
     (dict(precision=5), -1),
     (dict(dtau=0.002), -3),      # dtau * max T = 2.96 for H_K^(1) at a = 0.1
     (dict(kin=3, dtau=0.06, a=0.05), -3),
+    (dict(complex_psi=1, nstates=2), -1),   # a complex lattice holds one state
+    (dict(complex_psi=2), -1),
 ])
 def test_create_rejects_bad_descriptions(kw, status):
     st, msg = _create(**kw)

@@ -1,0 +1,213 @@
+"""GPU parity of complex states in complex potentials (the map of equation
+iter_proced with complex A and B; the paper's solver takes real and complex
+potentials), through the C ABI, against the FP64 oracle's complex map.
+
+A complex lattice holds Re psi and Im psi as two real arrays; the transform
+passes write K Re psi and K Im psi, one update kernel forms
+((1 - h V) psi - dtau K psi) / (1 + h V) with V = Vr + i Vi, and the finaliser
+reports one observable record with energy_imag = <psi|Vi psi>/<psi|psi>.
+
+Tolerances: FP64 lattices 1e-10 relative on energies and 1e-10 of the largest
+value on states; FP32 lattices (FP32 storage and transforms, FP64 sums) 1e-5 and
+1e-4, as for real states.  Energies are compared with max(1, |E|) scaling
+(energy_imag can be small)."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(np.asarray(b)).max(), 1e-300))
+
+
+def _dtau(kin, a, mass):
+    # inside the stability bound dtau * max T(k) <= 1.95 of every kinetic term used here
+    return a * a * mass / 8 if kin in (0, 1, 2) else a / 4
+
+
+def _lat(itse, n, prec, kin, a=0.25, mass=1.2, center="cell"):
+    return itse.Lattice(n, a, mass, _dtau(kin, a, mass), kin=kin, precision=prec, center=center,
+                        complex_psi=True)
+
+
+def _olat(orc, lat):
+    d = lat.desc
+    return orc.lattice(d.n, d.a, d.mass, d.dtau, d.kin, True, "cell" if d.center == 0 else "origin")
+
+
+def _inputs(n, a, center, prec, seed):
+    cdt = np.complex64 if prec == "fp32" else np.complex128
+    v = synth.potential_harmonic_complex(n, a, center, 0.5, 1.0).astype(cdt)
+    psi = synth.random_state_complex(n, seed, dtype=cdt)
+    return v, psi
+
+
+FIELDS = ("energy", "energy_imag", "kinetic", "potential", "norm2")
+MOMENTS = ("x", "y", "z", "r2", "parity_even")
+
+
+@pytest.mark.parametrize("n,prec,kin,center,parity,moments", [
+    (8, "fp64", 3, "cell", 0, True),
+    (24, "fp64", 3, "cell", 0, True),
+    (32, "fp32", 2, "origin", -1, True),
+    (48, "fp64", 1, "cell", 1, False),
+    (96, "fp32", 3, "origin", 0, False),
+    (32, "fp64", 0, "cell", 0, True),
+    (48, "fp32", 0, "origin", 1, True),
+])
+def test_complex_steps(itse, orc, n, prec, kin, center, parity, moments):
+    """Per-step observables (complex energy, kinetic, potential, norm, moments) and
+    the final complex state follow the oracle."""
+    steps, a = 8, 0.25
+    lat = _lat(itse, n, prec, kin, a=a, center=center)
+    v, psi = _inputs(n, a, center, prec, 40 + n + kin)
+    lat.set_potential(v)
+    lat.set_state(0, psi)
+    lat.set_options(moments=moments, parity=(parity,), axes=(7,))
+    lat.step(steps)
+    hist = lat.history(steps)
+    ostate, ohist = orc.step_complex(_olat(orc, lat), psi.astype(np.complex128), v.astype(np.complex128), steps,
+                                     parity=parity, axes=7, moments=moments)
+    etol = 1e-10 if prec == "fp64" else 1e-5
+    fields = FIELDS + (MOMENTS if moments else ())
+    if kin == 0:
+        fields = tuple(f for f in fields if f != "parity_even")  # not formed by H_K^(0) steps
+    for s in range(steps):
+        for f in fields:
+            g, r = hist[s][0][f], ohist[s][f]
+            assert abs(g - r) <= etol * max(1.0, abs(r)), (s, f, g, r)
+        if kin == 0:
+            assert hist[s][0]["parity_even"] == -1.0
+    got = lat.get_state(0)
+    assert np.iscomplexobj(got)
+    assert _rel(got, ostate) < (1e-10 if prec == "fp64" else 1e-4)
+    assert abs(np.sum(np.abs(got) ** 2) - 1.0) < (1e-12 if prec == "fp64" else 1e-5)
+    lat.close()
+
+
+def test_complex_evaluate(itse, orc):
+    """evaluate(): the observables of the current complex state without a step."""
+    n, a = 32, 0.25
+    lat = _lat(itse, n, "fp64", 3, a=a)
+    v, psi = _inputs(n, a, "cell", "fp64", 7)
+    lat.set_potential(v)
+    lat.set_state(0, psi)
+    lat.evaluate(moments=True)
+    o = lat.observe(0)
+    _, rec = orc.step_complex(_olat(orc, lat), psi, v, 1, moments=True)
+    for f in FIELDS + MOMENTS:
+        assert abs(o[f] - rec[0][f]) <= 1e-10 * max(1.0, abs(rec[0][f])), f
+    assert lat.step_count == 0
+    lat.close()
+
+
+def test_complex_kinetic_parts(itse, orc):
+    """apply_kinetic on index 0 / 1 of a complex lattice is H_K of Re psi / Im psi."""
+    n, a = 48, 0.25
+    lat = _lat(itse, n, "fp64", 3, a=a)
+    _, psi = _inputs(n, a, "cell", "fp64", 9)
+    lat.set_state(0, psi)
+    ol = _olat(orc, lat)
+    for part, arr in ((0, psi.real), (1, psi.imag)):
+        got = lat.apply_kinetic(part).cpu().numpy()
+        assert _rel(got, orc.apply_kinetic(ol, arr)) < 1e-12
+    lat.close()
+
+
+def test_complex_large_first_steps(itse, orc):
+    """256^3 FP32, relativistic lattice kinetic term, complex oscillator potential:
+    the first steps' complex energies match the FP64 oracle on the same FP32 inputs;
+    sampled sites of the state after them too."""
+    n, a = 256, 0.05
+    lat = _lat(itse, n, "fp32", 3, a=a, mass=1.3, center="origin")
+    v, psi = _inputs(n, a, "origin", "fp32", 11)
+    lat.set_potential(v)
+    lat.set_state(0, psi)
+    lat.step(2)
+    hist = lat.history(2)
+    ostate, ohist = orc.step_complex(_olat(orc, lat), psi.astype(np.complex128), v.astype(np.complex128), 2)
+    for s in range(2):
+        for f in ("energy", "energy_imag", "kinetic", "potential"):
+            g, r = hist[s][0][f], ohist[s][f]
+            assert abs(g - r) <= 1e-5 * max(1.0, abs(r)), (s, f, g, r)
+    got = lat.get_state(0)
+    rng = np.random.default_rng(5)
+    idx = tuple(rng.integers(0, n, size=(3, 4096)))
+    assert _rel(got[idx], ostate[idx]) < 1e-3
+    lat.close()
+
+
+def test_complex_in_batch_matches_alone(itse):
+    """Complex lattices group apart from real ones in a batch and give the same
+    results bitwise as stepped alone."""
+    def make(n, kin, cplx):
+        a = 0.25
+        lat = itse.Lattice(n, a, 1.2, _dtau(kin, a, 1.2), kin=kin, precision="fp32", center="cell",
+                           nstates=1, complex_psi=cplx)
+        if cplx:
+            v, psi = _inputs(n, a, "cell", "fp32", n + kin)
+        else:
+            v = synth.potential_harmonic(n, a, "cell", 0.5).astype(np.float32)
+            psi = synth.random_state(n, n + kin, dtype=np.float32)
+        lat.set_potential(v)
+        lat.set_state(0, psi)
+        lat.set_options(parity=(-1,))
+        return lat
+    specs = ((32, 3, True), (32, 3, False), (48, 0, True), (32, 2, True))
+    mk = [make(*sp) for sp in specs]
+    alone = [make(*sp) for sp in specs]
+    for lat in alone:
+        lat.step(20)
+    batch = itse.Batch(mk)
+    batch.step(20)
+    for la, lb, sp in zip(mk, alone, specs):
+        ga, gb = la.get_state(0, np.float32), lb.get_state(0, np.float32)
+        assert np.array_equal(ga, gb), sp
+        assert la.observe(0)["energy_imag"] == lb.observe(0)["energy_imag"]
+    batch.close()
+    for lat in mk + alone:
+        lat.close()
+
+
+def test_complex_oscillator_ground_state(itse):
+    """Physics check: H = p^2/(2M) + c (1 + i) r^2 (continuum kinetic term H_K^(1))
+    has the eigenvalues (n + 3/2) omega with omega = sqrt(2 c (1 + i) / M) (principal
+    root); the state of smallest real part dominates the map, so the complex energy
+    converges to 1.5 omega.  The map's fixed point is an eigenvector of
+    K + (1 + lambda) V / 2 rather than of H (lambda = 1 - O(dtau)), which shifts
+    the energy by O(dtau |E| |V|): 5e-3 of |E| at dtau = 2.5e-3."""
+    n, a, m, c = 64, 0.15, 1.0, 0.5
+    lat = itse.Lattice(n, a, m, 2.5e-3, kin=itse.KIN_NR_CONT, precision="fp64", center="cell",
+                       complex_psi=True)
+    v = synth.potential_harmonic_complex(n, a, "cell", c, 1.0)
+    _, _, _, r = synth.radius_grid(n, a, "cell")
+    lat.set_potential(v)
+    lat.set_state(0, np.exp(-0.5 * r * r).astype(np.complex128))
+    lat.set_options(parity=(1,))
+    lat.step(10000)
+    o = lat.observe(0)
+    e = complex(o["energy"], o["energy_imag"])
+    exact = 1.5 * np.sqrt(2 * c * (1 + 1j) / m)
+    assert abs(e - exact) < 5e-3 * abs(exact), (e, exact)
+    lat.close()
+
+
+def test_complex_errors(itse):
+    """Argument and state errors of the complex entry points."""
+    with pytest.raises(itse.ItseError, match="EINVAL"):
+        itse.Lattice(16, 0.25, 1.2, 0.05, kin=3, precision="fp32", nstates=2, complex_psi=True)
+    real = itse.Lattice(16, 0.25, 1.2, 0.05, kin=3, precision="fp32")
+    with pytest.raises(itse.ItseError, match="ESTATE"):
+        real.set_potential_imag(np.zeros((16, 16, 16), np.float32))
+    real.close()
+    lat = _lat(itse, 16, "fp32", 3)
+    with pytest.raises(itse.ItseError, match="ESTATE"):
+        lat.analyse(0)
+    with pytest.raises(itse.ItseError, match="ESTATE"):
+        lat.project_parity(0, 1)
+    with pytest.raises(itse.ItseError, match="EINVAL"):
+        lat.observe(1)
+    lat.close()

@@ -69,6 +69,8 @@ def test_fdtd_multistate_steps(itse, orc, n, prec, center, parity, axes):
             for f in ("energy", "norm2", "x", "r2"):
                 g, r = hist[s][i][f], ohist[s][i][f]
                 assert abs(g - r) <= etol * max(1.0, abs(r)), (s, i, f, g, r)
+            # no column pass: the parity weight is reported as not formed
+            assert hist[s][i]["parity_even"] == -1.0
     for i in range(3):
         assert _rel(lat.get_state(i), ostates[i]) < (1e-10 if prec == "fp64" else 1e-4)
     lat.close()

@@ -287,3 +287,24 @@ def test_complex_constant_potential_closed_form(orc):
     assert np.abs(out - (lam / abs(lam)) ** 7 * wave).max() < 1e-13
     for r in rec:
         assert abs(r["energy"] - (T + v0.real)) < 1e-12 and abs(r["energy_imag"] - v0.imag) < 1e-12
+
+
+def test_complex_map_global_phase(orc):
+    """A real potential and a state e^{i theta} phi: the map is complex-linear with
+    real A, B and H_K, so the result is e^{i theta} times the real map of phi, and
+    every observable (moments and parity weight included) is that of phi."""
+    n, a = 12, 0.3
+    L = orc.lattice(n, a, 1.2, dtau=a * a * 1.2 / 8, kin=3, center="origin")
+    v = synth.potential_harmonic(n, a, "origin", 0.5)
+    phi = synth.random_state(n, 5)
+    ph = np.exp(0.7j)
+    out_c, rec_c = orc.step_complex(L, ph * phi, v, 4, parity=-1, axes=7, moments=True)
+    out_r, rec_r = orc.step(L, [phi], v, 4, parity=[-1], axes=[7])
+    assert np.abs(out_c - ph * out_r[0]).max() < 1e-14
+    ob = orc.observe(L, [phi], v)[0]
+    for k in ("x", "y", "z", "r2", "parity_even"):
+        assert abs(rec_c[0][k] - ob[k]) < 1e-12, k
+    for s in range(4):
+        for k in ("energy", "kinetic", "potential"):
+            assert abs(rec_c[s][k] - rec_r[s][0][k]) < 1e-12, (s, k)
+        assert abs(rec_c[s]["energy_imag"]) < 1e-15
