@@ -445,6 +445,29 @@ def main():
         "k1_hbm_frac": 12.0 * n ** 3 / (secsf1 / args.steps) / 1e9 / HBM_PEAK_GBS,
     }
 
+    # one complex state in a complex potential (Re V the workload's potential, Im V
+    # = 0.5 r^2, the paper's complex-oscillator shape): transforms of Re psi and Im
+    # psi to K psi, then the complex update, which reads Re psi, Im psi, K Re psi,
+    # K Im psi, Re V, Im V and writes Re psi', Im psi' (32 bytes per site in FP32)
+    import synth
+    latc = itse.Lattice(n, p.a, p.mass, p.dtau, kin=p.kin, subtract_rest_mass=p.subtract_rest_mass,
+                        precision="fp32", center=p.center, complex_psi=True)
+    vci = synth.potential_harmonic_complex(n, p.a, p.center, 0.5, 1.0).imag.astype(np.float32)
+    latc.set_potential(v32.astype(np.float32) + 1j * vci)
+    latc.set_state(0, st32[0] + 1j * st32[1])
+    latc.set_options(moments=False, parity=(p.parity[0],))
+    secsc = timed_steps(torch, latc, args.steps, args.warmup)
+    profc = latc.profile_step(args.profile_steps)
+    latc.close()
+    cu_bytes = 32.0 * n ** 3
+    extra["complex"] = {
+        "site_steps_per_s": n ** 3 * args.steps / secsc,
+        "ms_per_step": secsc * 1000.0 / args.steps,
+        "passes_ms": profc,
+        "k_complex_update_gbs": cu_bytes / (profc["k_complex_update"] * 1e-3) / 1e9,
+        "k_complex_update_frac": cu_bytes / (profc["k_complex_update"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+    }
+
     out = {
         "metric": "site-steps/s at 256^3 (FP32 steps with FP64 reductions)",
         "value": value,
