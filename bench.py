@@ -95,6 +95,31 @@ def make_lattice(itse, p, v, states, fp32: bool):
     return lat
 
 
+def make_fdtd_lattice(itse, p, v, states, nstates=None):
+    """The workload with H_K^(0) (finite differences, Dirichlet walls) and the
+    dtau = a^2 M / 8 its stability bound allows; nstates=1 gives the bare step."""
+    import dataclasses
+    pf = dataclasses.replace(p, kin=0, dtau=p.a * p.a * p.mass / 8)
+    if nstates == 1:
+        pf = dataclasses.replace(pf, nstates=1, parity=(0,))
+        states = states[:1]
+    return make_lattice(itse, pf, v, states, fp32=True)
+
+
+def make_complex_lattice(itse, p, v, states):
+    """One complex state at the workload's size: Re V the workload's potential,
+    Im V = 0.5 r^2 (the paper's complex-oscillator shape), psi = states[0] + i
+    states[1], parity of state 0."""
+    import synth
+    lat = itse.Lattice(p.n, p.a, p.mass, p.dtau, kin=p.kin, subtract_rest_mass=p.subtract_rest_mass,
+                       precision="fp32", center=p.center, complex_psi=True)
+    vi = synth.potential_harmonic_complex(p.n, p.a, p.center, 0.5, 1.0).imag.astype(np.float32)
+    lat.set_potential(v.astype(np.float32) + 1j * vi)
+    lat.set_state(0, states[0] + 1j * states[1])
+    lat.set_options(moments=False, parity=(p.parity[0],))
+    return lat
+
+
 def timed_steps(torch, lat, steps: int, warmup: int):
     lat.step(warmup)
     lat.sync()
@@ -295,6 +320,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=288.0)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only step the 256^3 FP32 workload a few times and profile its passes (for rocprofv3)")
+    ap.add_argument("--form", choices=["precision", "fdtd", "complex"], default="precision",
+                    help="with --kernels-only: the workload (precision), its H_K^(0) form, or one complex state")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 256 MiB five times (scale for HBM counters)")
     args = ap.parse_args()
@@ -330,7 +357,12 @@ def main():
         # eager launches of each pass (schedule from --schedule, default 2)
         itse.set_schedule(n, "fp32", args.schedule if args.schedule >= 0 else 2)
         p, v32, st32 = build_workload(n, fp32=True)
-        lat = make_lattice(itse, p, v32, st32, fp32=True)
+        if args.form == "fdtd":
+            lat = make_fdtd_lattice(itse, p, v32, st32)
+        elif args.form == "complex":
+            lat = make_complex_lattice(itse, p, v32, st32)
+        else:
+            lat = make_lattice(itse, p, v32, st32, fp32=True)
         lat.step(2)
         prof = lat.profile_step(args.profile_steps)
         lat.close()
@@ -422,13 +454,11 @@ def main():
     # H_K^(0) (finite differences, Dirichlet walls): the same three-state workload
     # with one fused stencil pass per state instead of the transforms, and the bare
     # one-state step (12 bytes per site in FP32: psi, V, psi')
-    pf = dataclasses.replace(p, kin=0, dtau=p.a * p.a * p.mass / 8)
-    latf = make_lattice(itse, pf, v32, st32, fp32=True)
+    latf = make_fdtd_lattice(itse, p, v32, st32)
     secsf = timed_steps(torch, latf, args.steps, args.warmup)
     proff = latf.profile_step(args.profile_steps)
     latf.close()
-    pf1 = dataclasses.replace(pf, nstates=1, parity=(0,))
-    latf1 = make_lattice(itse, pf1, v32, st32[:1], fp32=True)
+    latf1 = make_fdtd_lattice(itse, p, v32, st32, nstates=1)
     secsf1 = timed_steps(torch, latf1, args.steps, args.warmup)
     proff1 = latf1.profile_step(args.profile_steps)
     latf1.close()
@@ -449,13 +479,7 @@ def main():
     # = 0.5 r^2, the paper's complex-oscillator shape): transforms of Re psi and Im
     # psi to K psi, then the complex update, which reads Re psi, Im psi, K Re psi,
     # K Im psi, Re V, Im V and writes Re psi', Im psi' (32 bytes per site in FP32)
-    import synth
-    latc = itse.Lattice(n, p.a, p.mass, p.dtau, kin=p.kin, subtract_rest_mass=p.subtract_rest_mass,
-                        precision="fp32", center=p.center, complex_psi=True)
-    vci = synth.potential_harmonic_complex(n, p.a, p.center, 0.5, 1.0).imag.astype(np.float32)
-    latc.set_potential(v32.astype(np.float32) + 1j * vci)
-    latc.set_state(0, st32[0] + 1j * st32[1])
-    latc.set_options(moments=False, parity=(p.parity[0],))
+    latc = make_complex_lattice(itse, p, v32, st32)
     secsc = timed_steps(torch, latc, args.steps, args.warmup)
     profc = latc.profile_step(args.profile_steps)
     latc.close()
