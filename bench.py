@@ -476,20 +476,22 @@ def main():
     }
 
     # one complex state in a complex potential (Re V the workload's potential, Im V
-    # = 0.5 r^2, the paper's complex-oscillator shape): transforms of Re psi and Im
-    # psi to K psi, then the complex update, which reads Re psi, Im psi, K Re psi,
-    # K Im psi, Re V, Im V and writes Re psi', Im psi' (32 bytes per site in FP32)
+    # = 0.5 r^2, the paper's complex-oscillator shape): both parts forward, the real
+    # part's inverse pass writing K Re psi, then the imaginary part's inverse pass
+    # applying the complex update to both parts.  The two inverse passes move 48
+    # bytes per site in FP32: spectra 8, Re psi twice 8, Im psi 4, Re V twice 8,
+    # Im V 4, K Re psi written and read 8, both new parts 8
     latc = make_complex_lattice(itse, p, v32, st32)
     secsc = timed_steps(torch, latc, args.steps, args.warmup)
     profc = latc.profile_step(args.profile_steps)
     latc.close()
-    cu_bytes = 32.0 * n ** 3
+    inv_bytes = (48.0 + 16.0 / n) * n ** 3
     extra["complex"] = {
         "site_steps_per_s": n ** 3 * args.steps / secsc,
         "ms_per_step": secsc * 1000.0 / args.steps,
         "passes_ms": profc,
-        "k_complex_update_gbs": cu_bytes / (profc["k_complex_update"] * 1e-3) / 1e9,
-        "k_complex_update_frac": cu_bytes / (profc["k_complex_update"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "inverse_passes_gbs": inv_bytes / (profc["k_plane_inv"] * 1e-3) / 1e9,
+        "inverse_passes_frac": inv_bytes / (profc["k_plane_inv"] * 1e-3) / 1e9 / HBM_PEAK_GBS,
     }
 
     out = {

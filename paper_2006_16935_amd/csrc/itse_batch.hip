@@ -141,9 +141,16 @@ extern "C" itse_status itse_batch_create(int count, itse_lattice *const *lats, v
     for (auto &key : order) {
         auto &members = by[key];
         std::vector<JobRef> jobs, lrefs;
-        for (auto *L : members) {
-            for (int i = 0; i < L->d.nstates; ++i) jobs.push_back(JobRef{L->dev, i, 0});
-            lrefs.push_back(JobRef{L->dev, 0, 0});
+        if (std::get<3>(key) & 2) {
+            // complex lattices: every lattice's real part, then every imaginary part
+            for (int i = 0; i < 2; ++i)
+                for (auto *L : members) jobs.push_back(JobRef{L->dev, i, 0});
+            for (auto *L : members) lrefs.push_back(JobRef{L->dev, 0, 0});
+        } else {
+            for (auto *L : members) {
+                for (int i = 0; i < L->d.nstates; ++i) jobs.push_back(JobRef{L->dev, i, 0});
+                lrefs.push_back(JobRef{L->dev, 0, 0});
+            }
         }
         JobRef *dj = nullptr, *dl = nullptr;
         if (hipMalloc(&dj, jobs.size() * sizeof(JobRef)) != hipSuccess ||
@@ -160,6 +167,7 @@ extern "C" itse_status itse_batch_create(int count, itse_lattice *const *lats, v
         g.variant = std::get<2>(key);
         g.fdtd = (std::get<3>(key) & 1) != 0;
         g.cplx = (std::get<3>(key) & 2) != 0;
+        g.nb_cplx = members[0]->host.nb_cplx;
         g.jobs = dj;
         g.njobs = (int)jobs.size();
         g.lats = dl;

@@ -59,7 +59,8 @@ struct LatDev {
     void *vi;
     void *kbuf;
     double *part_cplx;   // [nb_cplx][NQX]
-    int nb_cplx;
+    int nb_cplx;         // transform lattices: nb_rows (one partial per imaginary-part
+                         // plane workgroup); H_K^(0) lattices: flat_blocks(n)
     // reduction arena
     double *part_rows;   // [MAXK][nb_rows][NQR]
     double *part_cols;   // [MAXK][nb_cols][NQC]
@@ -123,9 +124,14 @@ struct Launch {
     static hipError_t project_gram(int n, int kmax, const JobRef *lats, int nlats, int force, int which,
                                    hipStream_t s);
     static hipError_t combine(int n, const JobRef *jobs, int njobs, void *const *outs, hipStream_t s);
-    // complex lattices: the complex update after the transforms in mode INV_KBUF
-    // (mode INV_UPDATE or INV_EVAL); flat_blocks(n) workgroups per lattice
-    static hipError_t complex_update(int n, const JobRef *lats, int nlats, int mode, hipStream_t s);
+    // complex lattices: the imaginary parts' inverse pass with the complex update
+    // (jobs: state 1 of each lattice; after the real parts' pass in mode INV_KBUF;
+    // without position moments)
+    static hipError_t plane_inv_cplx(int n, int variant, const JobRef *jobs, int njobs, hipStream_t s);
+    // complex lattices: the separate complex update after the transforms in mode
+    // INV_KBUF (mode INV_UPDATE or INV_EVAL); nb workgroups per lattice, the
+    // lattices' nb_cplx
+    static hipError_t complex_update(int n, int nb, const JobRef *lats, int nlats, int mode, hipStream_t s);
     // H_K^(0) lattices: stencil, update and sums in one pass (modes of plane_inv)
     static hipError_t fdtd(int n, int kmax, int mode, const JobRef *jobs, int njobs, hipStream_t s);
     static int fdtd_blocks(int n);

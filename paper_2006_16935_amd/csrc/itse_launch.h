@@ -192,6 +192,26 @@ hipError_t Launch<R>::plane_inv(int n, int variant, int mode, int moments, int k
 }
 
 template <typename R>
+struct PlaneInvCplxF {
+    const JobRef *jobs;
+    int njobs;
+    hipStream_t s;
+    template <int N, int V>
+    hipError_t operator()() {
+        using G = Geo<R, N, V>;
+        hipLaunchKernelGGL((k_plane_inv<R, N, V, false, 4, true>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0, s,
+                           jobs, (int)INV_UPDATE);
+        return hipGetLastError();
+    }
+};
+
+template <typename R>
+hipError_t Launch<R>::plane_inv_cplx(int n, int variant, const JobRef *jobs, int njobs, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    return dispatch<R>(n, variant, PlaneInvCplxF<R>{jobs, njobs, s});
+}
+
+template <typename R>
 hipError_t Launch<R>::project(int n, const JobRef *jobs, int njobs, int force_sign, int force_axes, int which,
                               hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
@@ -304,9 +324,9 @@ hipError_t Launch<R>::combine(int n, const JobRef *jobs, int njobs, void *const 
 }
 
 template <typename R>
-hipError_t Launch<R>::complex_update(int n, const JobRef *lats, int nlats, int mode, hipStream_t s) {
+hipError_t Launch<R>::complex_update(int n, int nb, const JobRef *lats, int nlats, int mode, hipStream_t s) {
     if (nlats <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_complex_update<R>), dim3(flat_blocks(n), nlats), dim3(NT), 0, s, lats, mode);
+    hipLaunchKernelGGL((k_complex_update<R>), dim3(nb, nlats), dim3(NT), 0, s, lats, mode);
     return hipGetLastError();
 }
 

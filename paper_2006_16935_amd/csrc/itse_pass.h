@@ -807,7 +807,12 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
 // ---------------------------------------------------------------------------
 // MOM: position moments summed (the lattices' moments flag); without them the
 // update loop has the registers to take two chunks per load round.
-template <typename R, int N, int V, bool MOM, int KM>
+// CPX: the imaginary part (state 1) of complex lattices, after the real part's
+// pass has written K Re psi to kbuf: with Re psi = c u_0, Im psi = c u_1 and
+// V = Vr + i Vi it applies the complex map ((1 - h V) psi - dtau K psi)/(1 + h V)
+// and writes both parts' new arrays; besides its own row sums it forms
+// sum Vi |psi|^2 and sum |psi'|^2 (the complex-update sums).
+template <typename R, int N, int V, bool MOM, int KM, bool CPX = false>
 __global__ void __launch_bounds__((Geo<R, N, V>::NTP)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPE)))
 k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     using G = Geo<R, N, V>;
@@ -876,9 +881,16 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     double acc[NQR];
 #pragma unroll
     for (int q = 0; q < NQR; ++q) acc[q] = 0.0;
-    using PC = PairChunks<R, N, PPW, MOM ? 1 : 2>;
+    using PC = PairChunks<R, N, PPW, (MOM || CPX) ? 1 : 2>;
     constexpr int VL = PC::VL, GG = PC::G;
     const double cx = site_coord(x, N, center, a);
+    // CPX: the real part's raw array and K psi, Im V, the real part's new array
+    const double c0 = CPX ? L.coef[0][0] : 0.0;
+    const ITSE_GLOBAL R *u0c = gmem((const R *)state_buf(L, L.step, 0, 0));
+    const ITSE_GLOBAL R *krc = gmem((const R *)L.kbuf);
+    const ITSE_GLOBAL R *vic = gmem((const R *)L.vi);
+    ITSE_GLOBAL R *w0c = gmem((R *)state_buf(L, L.step, 1, 0));
+    double xacc[NQX] = {0.0, 0.0};
 #pragma unroll 1
     for (int gi = 0; gi < PC::GROUPS; ++gi) {
         size_t o0[GG], o1[GG];
@@ -899,16 +911,25 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
         R ph[2][GG][VL];
         lazy_rows<R, GG>(vw, o0, o1, ok, ph[0], ph[1]);
         Vec<R> vv[2][GG];
+        Vec<R> xr[2][GG], xk[2][GG], xi[2][GG];  // CPX: u_0, K Re psi, Im V
 #pragma unroll
         for (int t = 0; t < GG; ++t)
             if (ok[t]) {
                 vv[0][t] = *(const ITSE_GLOBAL Vec<R> *)(v + o0[t]);
                 vv[1][t] = *(const ITSE_GLOBAL Vec<R> *)(v + o1[t]);
+                if constexpr (CPX) {
+                    xr[0][t] = *(const ITSE_GLOBAL Vec<R> *)(u0c + o0[t]);
+                    xr[1][t] = *(const ITSE_GLOBAL Vec<R> *)(u0c + o1[t]);
+                    xk[0][t] = *(const ITSE_GLOBAL Vec<R> *)(krc + o0[t]);
+                    xk[1][t] = *(const ITSE_GLOBAL Vec<R> *)(krc + o1[t]);
+                    xi[0][t] = *(const ITSE_GLOBAL Vec<R> *)(vic + o0[t]);
+                    xi[1][t] = *(const ITSE_GLOBAL Vec<R> *)(vic + o1[t]);
+                }
             }
 #pragma unroll
         for (int t = 0; t < GG; ++t) {
             if (!ok[t]) continue;
-            Vec<R> un[2], kv[2];
+            Vec<R> un[2], kv[2], unr[2];
 #pragma unroll
             for (int k = 0; k < VL; ++k) {
                 const C2<R> kp = buf[lp[t] + k];
@@ -924,7 +945,23 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
                     const R vr = vv[row][t][k];
                     const R kr = kv[row][k];
                     const R hv = h * vr;
-                    const R unv = div_fast<R>(p_ * ((R)1 - hv) - dt * kr, (R)1 + hv);
+                    R unv;
+                    if constexpr (CPX) {
+                        // p_ = Im psi, kr = K Im psi; the real part from u_0 and kbuf
+                        const R pr = (R)(c0 * (double)xr[row][t][k]);
+                        const R hi = h * xi[row][t][k];
+                        const R nr = pr * ((R)1 - hv) + hi * p_ - dt * xk[row][t][k];
+                        const R ni = p_ * ((R)1 - hv) - hi * pr - dt * kr;
+                        const R dr = (R)1 + hv;
+                        const R inv = div_fast<R>((R)1, dr * dr + hi * hi);
+                        const R ur = (nr * dr + ni * hi) * inv;
+                        unv = (ni * dr - nr * hi) * inv;
+                        unr[row][k] = ur;
+                        xacc[XQ_VIPP] += (double)xi[row][t][k] * ((double)pr * (double)pr + (double)p_ * (double)p_);
+                        xacc[XQ_UU] += (double)ur * (double)ur + (double)unv * (double)unv;
+                    } else {
+                        unv = div_fast<R>(p_ * ((R)1 - hv) - dt * kr, (R)1 + hv);
+                    }
                     un[row][k] = unv;
                     const double pd = (double)p_;
                     acc[RQ_PP] += pd * pd;
@@ -944,6 +981,10 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
             if (mode == INV_UPDATE) {
                 *(ITSE_GLOBAL Vec<R> *)(u + o0[t]) = un[0];
                 *(ITSE_GLOBAL Vec<R> *)(u + o1[t]) = un[1];
+                if constexpr (CPX) {
+                    *(ITSE_GLOBAL Vec<R> *)(w0c + o0[t]) = unr[0];
+                    *(ITSE_GLOBAL Vec<R> *)(w0c + o1[t]) = unr[1];
+                }
             } else if (mode >= INV_KOUT) {
                 *(ITSE_GLOBAL Vec<R> *)(kout + o0[t]) = kv[0];
                 *(ITSE_GLOBAL Vec<R> *)(kout + o1[t]) = kv[1];
@@ -951,6 +992,10 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
         }
     }
     block_sums<NQR, NTP>(acc, L.part_rows + ((size_t)i * L.nb_rows + spb) * NQR, red);
+    if constexpr (CPX) {
+        __syncthreads();
+        block_sums<NQX, NTP>(xacc, L.part_cplx + (size_t)spb * NQX, red);
+    }
 }
 
 // ---------------------------------------------------------------------------

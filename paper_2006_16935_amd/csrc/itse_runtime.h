@@ -28,7 +28,8 @@ struct Group {
     int kmax = 1;                  // largest number of states among the lattices
     int needs = NEED_PROJECT | NEED_GRAM | NEED_MOMENTS;  // optional work of a step
     bool fdtd = false;             // H_K^(0): one stencil pass instead of the transforms
-    bool cplx = false;             // complex lattices: transforms to kbuf, complex update
+    bool cplx = false;             // complex lattices (jobs: every lattice's state 0, then every state 1)
+    int nb_cplx = 0;               // complex lattices: workgroups of the separate complex update
 };
 
 itse_status fail(itse_status st, const char *fmt, ...);

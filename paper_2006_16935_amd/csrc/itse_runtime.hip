@@ -386,14 +386,33 @@ int step_needs(const LatDev &o, int nstates) {
     return m;
 }
 
+// Complex lattices: the transforms and the complex update.  Transform lattices
+// without position moments: both parts forward, the real parts' inverse pass
+// writing K Re psi to kbuf, then the imaginary parts' inverse pass, which applies
+// the complex update to both parts.  Otherwise (H_K^(0), or moments, whose sums
+// leave no registers for the fused update): K psi of both parts to kbuf, then the
+// separate complex update.
+static bool cplx_fused(const Group &g) { return !g.fdtd && !(g.needs & NEED_MOMENTS); }
+
+template <typename R>
+static hipError_t seq_cplx_update(const Group &g, hipStream_t s) {
+    hipError_t e;
+    if (!cplx_fused(g)) {
+        if ((e = seq_forward_kin<R>(g, INV_KBUF, s)) != hipSuccess) return e;
+        return Launch<R>::complex_update(g.n, g.nb_cplx, g.lats, g.nlats, INV_UPDATE, s);
+    }
+    if ((e = Launch<R>::plane_fwd(g.n, g.variant, g.kmax, g.jobs, g.njobs, s)) != hipSuccess) return e;
+    if ((e = Launch<R>::columns(g.n, g.variant, COL_KIN, 1, g.jobs, g.njobs, nullptr, s)) != hipSuccess) return e;
+    if ((e = Launch<R>::plane_inv(g.n, g.variant, INV_KBUF, 0, g.kmax, g.jobs, g.nlats, s)) != hipSuccess) return e;
+    return Launch<R>::plane_inv_cplx(g.n, g.variant, g.jobs + g.nlats, g.nlats, s);
+}
+
 template <typename R>
 static hipError_t seq_step(const Group &g, hipStream_t s) {
     hipError_t e;
     if (g.cplx) {
-        // complex lattices: K Re psi, K Im psi to kbuf, then the complex update;
         // projection (both parts, same sign and axes) with the norm in the Gram pass
-        if ((e = seq_forward_kin<R>(g, INV_KBUF, s)) != hipSuccess) return e;
-        if ((e = Launch<R>::complex_update(g.n, g.lats, g.nlats, INV_UPDATE, s)) != hipSuccess) return e;
+        if ((e = seq_cplx_update<R>(g, s)) != hipSuccess) return e;
         if ((g.needs & NEED_GRAM) &&
             (e = Launch<R>::project_gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s)) != hipSuccess)
             return e;
@@ -416,8 +435,8 @@ hipError_t enqueue_eval(const Group &g, hipStream_t s) {
     const int mode = g.cplx ? INV_KBUF : INV_EVAL;
     hipError_t e = g.prec == ITSE_FP32 ? seq_forward_kin<float>(g, mode, s) : seq_forward_kin<double>(g, mode, s);
     if (e == hipSuccess && g.cplx)
-        e = g.prec == ITSE_FP32 ? Launch<float>::complex_update(g.n, g.lats, g.nlats, INV_EVAL, s)
-                                : Launch<double>::complex_update(g.n, g.lats, g.nlats, INV_EVAL, s);
+        e = g.prec == ITSE_FP32 ? Launch<float>::complex_update(g.n, g.nb_cplx, g.lats, g.nlats, INV_EVAL, s)
+                                : Launch<double>::complex_update(g.n, g.nb_cplx, g.lats, g.nlats, INV_EVAL, s);
     if (e != hipSuccess) return e;
     return launch_finalize(g.lats, g.nlats, FIN_EVAL, s);
 }
@@ -507,6 +526,7 @@ Group single_group(itse_lattice *L) {
     g.needs = step_needs(L->host, L->d.nstates);
     g.fdtd = L->d.kin == ITSE_KIN_FDTD;
     g.cplx = L->host.cplx != 0;
+    g.nb_cplx = L->host.nb_cplx;
     return g;
 }
 
@@ -543,6 +563,7 @@ extern "C" size_t itse_footprint_bytes(const itse_desc *d) {
     const size_t K = cplx ? 2 : (size_t)std::max(1, std::min(d->nstates, MAXK));
     const size_t spec = spec_bytes(d->n, d->precision);
     size_t arena = 0;
+    int rows_max = 0;
     if (prec_supported(d->n, d->precision)) {
         const int nv = d->precision == ITSE_FP32 ? Launch<float>::variants(d->n) : Launch<double>::variants(d->n);
         for (int v = 0; v < nv; ++v) {
@@ -553,13 +574,14 @@ extern "C" size_t itse_footprint_bytes(const itse_desc *d) {
             const size_t a = (size_t)MAXK * ((size_t)s.nb_rows * NQR + (size_t)s.nb_cols * NQC + s.nb_proj) * 8 +
                              (size_t)s.nb_gram * (MAXK * (MAXK + 1) / 2) * 8;
             arena = std::max(arena, a);
+            rows_max = std::max(rows_max, s.nb_rows);
         }
     }
     const size_t hist = (size_t)HIST_CAP * MAXK * sizeof(ObsDev);
     // per state: two raw arrays u_i (current, next) and the half spectrum; shared: potential, scratch array,
     // staging for a host upload in the other precision (n^3 doubles), partial sums, history
     // complex lattices also: Im V, K Re psi and K Im psi, the complex-update partials
-    const size_t cx = cplx ? 3 * n3 * w + (size_t)flat_blocks(d->n) * NQX * 8 : 0;
+    const size_t cx = cplx ? 3 * n3 * w + (size_t)std::max(flat_blocks(d->n), rows_max) * NQX * 8 : 0;
     return K * (2 * n3 * w + spec) + n3 * w + n3 * w + n3 * 8 + arena + hist + sizeof(LatDev) + 8192 + n * 8 + cx;
 }
 
@@ -644,7 +666,7 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
     H.hist = (ObsDev *)lat_alloc(L, (size_t)HIST_CAP * MAXK * sizeof(ObsDev));
     if (d->complex_psi) {
         H.cplx = 1;
-        H.nb_cplx = flat_blocks(n);
+        H.nb_cplx = d->kin == ITSE_KIN_FDTD ? flat_blocks(n) : H.nb_rows;
         H.vi = lat_alloc(L, n3 * w);
         H.kbuf = lat_alloc(L, 2 * n3 * w);
         H.part_cplx = (double *)lat_alloc(L, (size_t)H.nb_cplx * NQX * 8);
@@ -1376,14 +1398,20 @@ static hipError_t launch_pass(const Group &g, int p, hipStream_t s) {
     case 0: return Launch<R>::plane_fwd(g.n, g.variant, g.kmax, g.jobs, g.njobs, s);
     case 1: return Launch<R>::columns(g.n, g.variant, COL_KIN, 1, g.jobs, g.njobs, nullptr, s);
     case 2: {
+        const int mom = (g.needs & NEED_MOMENTS) ? 1 : 0;
+        if (g.cplx && cplx_fused(g)) {
+            // the real parts' pass, then the imaginary parts' pass with the complex update
+            hipError_t e = Launch<R>::plane_inv(g.n, g.variant, INV_KBUF, 0, g.kmax, g.jobs, g.nlats, s);
+            return e != hipSuccess ? e : Launch<R>::plane_inv_cplx(g.n, g.variant, g.jobs + g.nlats, g.nlats, s);
+        }
         const int mode = g.cplx ? INV_KBUF : INV_UPDATE;
         return g.fdtd ? Launch<R>::fdtd(g.n, g.kmax, mode, g.jobs, g.njobs, s)
-                      : Launch<R>::plane_inv(g.n, g.variant, mode, (g.needs & NEED_MOMENTS) ? 1 : 0, g.kmax,
-                                             g.jobs, g.njobs, s);
+                      : Launch<R>::plane_inv(g.n, g.variant, mode, mom, g.kmax, g.jobs, g.njobs, s);
     }
     case 3:
-        // complex lattices: the complex update takes the slot of the per-state projection
-        if (g.cplx) return Launch<R>::complex_update(g.n, g.lats, g.nlats, INV_UPDATE, s);
+        // the separate complex update takes the slot of the per-state projection
+        if (g.cplx && !cplx_fused(g))
+            return Launch<R>::complex_update(g.n, g.nb_cplx, g.lats, g.nlats, INV_UPDATE, s);
         return (g.needs & NEED_PROJECT) ? Launch<R>::project(g.n, g.jobs, g.njobs, 0, 0, 1, s) : hipSuccess;
     case 4:
         return (g.needs & NEED_GRAM) ? Launch<R>::project_gram(g.n, g.kmax, g.lats, g.nlats, 0, 1, s) : hipSuccess;
@@ -1403,8 +1431,8 @@ extern "C" itse_status itse_profile_step(itse_lattice *L, int nsteps, double *ms
     // passes a step of these options does not launch are reported as 0
     bool launched[NPASS];
     for (int p = 0; p < NPASS; ++p)
-        launched[p] = !((p == 3 && !(g.needs & NEED_PROJECT) && !g.cplx) || (p == 4 && !(g.needs & NEED_GRAM)) ||
-                        (p < 2 && g.fdtd));
+        launched[p] = !((p == 3 && !(g.needs & NEED_PROJECT) && !(g.cplx && !cplx_fused(g))) ||
+                        (p == 4 && !(g.needs & NEED_GRAM)) || (p < 2 && g.fdtd));
     std::vector<hipEvent_t> ev((size_t)nsteps * (NPASS + 1));
     for (auto &e : ev) HIPCHK(hipEventCreate(&e));
     for (int s = 0; s < nsteps; ++s) {
@@ -1440,7 +1468,8 @@ extern "C" itse_status itse_profile_step(itse_lattice *L, int nsteps, double *ms
         std::string js = "[";
         for (int p = 0; p < NPASS; ++p)
             js += std::string(p ? ", " : "") + "\"" +
-                  (p == 2 && g.fdtd ? "k_fdtd" : p == 3 && g.cplx ? "k_complex_update" : pass_names[p]) + "\"";
+                  (p == 2 && g.fdtd ? "k_fdtd" : p == 3 && g.cplx && !cplx_fused(g) ? "k_complex_update" : pass_names[p]) +
+                  "\"";
         js += "]";
         snprintf(names, names_len, "%s", js.c_str());
     }
