@@ -268,3 +268,21 @@ def test_nonfinite_state_reported(itse):
         lat.observe(0)
     assert e.value.status == -4
     lat.close()
+
+
+def test_zero_state_reported_and_zero_steps(itse):
+    """Degenerate inputs: zero steps change nothing; a state that is zero everywhere
+    has no norm to normalise by, which the step reports as ITSE_ENONFINITE."""
+    n = 16
+    lat = _lat(itse, n)
+    psi = synth.random_state(n, 3)
+    lat.set_state(0, psi)
+    lat.step(0)
+    assert lat.step_count == 0
+    assert np.array_equal(lat.get_state(0), psi)
+    lat.set_state(0, np.zeros((n, n, n)))
+    lat.step(1)
+    with pytest.raises(itse.ItseError) as e:
+        lat.observe(0)
+    assert e.value.status == -4
+    lat.close()

@@ -96,7 +96,7 @@ def test_kinetic_schedules(itse, orc, n, prec, variant, kin):
 
 
 @pytest.mark.parametrize("n,prec,variant", [(96, "fp64", 0), (128, "fp64", 0), (128, "fp32", 1),
-                                            (192, "fp32", 0)])
+                                            (192, "fp32", 0), (256, "fp64", 0), (256, "fp64", 1)])
 def test_multistate_steps_large(itse, orc, n, prec, variant):
     """Three states (even, odd, odd deflated against the odd one), Cornell potential,
     a few steps: every step's energies and the final states match the oracle."""
