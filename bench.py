@@ -149,6 +149,42 @@ def cpu_baseline(p, v, states, budget_s: float = 30.0):
             "sample": f"1 step of all {p.nstates} states of the {p.n}^3 workload in FP64 ({dt:.1f} s)"}
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_scaling():
+    """The FP64 oracle at the smaller configuration sizes, on one thread and on all
+    threads: the plain 32^3 oscillator (one state, 20 steps) and the 128^3
+    relativistic Cornell solve (three states with Gram-Schmidt, 1 step); the 256^3
+    figure is the cpu_baseline (all threads only: one thread would take minutes)."""
+    import oracle
+    import synth
+    out = {"cpu_model": _cpu_model(), "nproc": os.cpu_count(), "runs": []}
+    all_threads = oracle.num_threads()
+    cases = [(synth.config_plain_fp64(), 20), (synth.config_relativistic_fp64(128), 1)]
+    for prob, steps in cases:
+        L = oracle.lattice(prob.n, prob.a, prob.mass, prob.dtau, prob.kin, prob.subtract_rest_mass, prob.center)
+        v = prob.potential_array(np.float64)
+        st = [s.astype(np.float64) for s in prob.initial_states()]
+        for threads in (1, all_threads):
+            oracle.set_num_threads(threads)
+            t0 = time.perf_counter()
+            oracle.step(L, st, v, steps, parity=list(prob.parity) if prob.parity else None,
+                        ortho_every=prob.ortho_every, record=False)
+            dt = time.perf_counter() - t0
+            out["runs"].append({"n": prob.n, "states": prob.nstates, "steps": steps, "threads": threads,
+                                "site_steps_per_s": prob.n ** 3 * prob.nstates * steps / dt})
+    oracle.set_num_threads(all_threads)
+    return out
+
+
 def batch_leg(torch, itse, steps: int, warmup: int, count: int = 64):
     """The batched form: `count` independent solves (N in {32, 48, 64, 96}, masses,
     Cornell couplings and kinetic terms drawn by synth.batch_problems), two states
@@ -449,6 +485,9 @@ def main():
         secs64 = timed_steps(torch, lat64, steps64, max(2, args.warmup // 2))
         extra["fp64_site_steps_per_s"] = sites * steps64 / secs64
         extra["fp64_ms_per_step"] = secs64 * 1000.0 / steps64
+        pb64 = sum(pass_bytes(n, 8, p.nstates, p.parity, p.ortho_every == 1).values())
+        extra["fp64_step_hbm_frac"] = pb64 / secs64 * steps64 / 1e9 / HBM_PEAK_GBS
+        extra["fp64_step_hbm_frac_compulsory"] = 24.0 * sites * steps64 / secs64 / 1e9 / HBM_PEAK_GBS
         lat64.close()
 
     # H_K^(0) (finite differences, Dirichlet walls): the same three-state workload
@@ -521,6 +560,9 @@ def main():
         "passes_bytes": pb,
         "step_bytes": step_bytes,
         "step_hbm_frac": step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        # against the compulsory floor of 12 bytes per site and state (psi in, V in,
+        # psi' out), which the transforms cannot reach when a plane does not fit on chip
+        "step_hbm_frac_compulsory": 12.0 * value / 1e9 / HBM_PEAK_GBS,
         "energies_fp32": e_fp32,
     }
     if not args.no_batch:
@@ -528,6 +570,7 @@ def main():
     out.update(extra)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, v32.astype(np.float64), [s.astype(np.float64) for s in st32])
+        out["oracle_scaling"] = oracle_scaling()
     print(json.dumps(out), flush=True)
 
 
