@@ -369,7 +369,8 @@ struct PairChunks {
 };
 
 // Copy of a contiguous global block of E complex values into LDS rows of length
-// RL with stride RS, all loads of the calling thread issued first.
+// RL with stride RS, all loads of the calling thread issued first (up to 16
+// 16-byte loads per thread in one batch: one memory round trip).
 // FP32 rows copied two values per thread (16-byte accesses): needs even strides
 // and, for rows of odd length, one slot of padding after each row in both layouts
 // (it receives the padding value of the other side, which nothing reads).
@@ -383,7 +384,7 @@ __device__ __forceinline__ void block_load_rows(const C2<R> *src_, C2<R> *dst, i
         static_assert(E % RL == 0, "whole rows");
         constexpr int RP = (RL + 1) / 2, EP = E / RL * RP;
         constexpr int T = (EP + NTH - 1) / NTH;
-        constexpr int TB = 8;
+        constexpr int TB = T < 16 ? T : 16;
         const ITSE_GLOBAL F4 *src = (const ITSE_GLOBAL F4 *)gmem(src_);
         F4 *d4 = (F4 *)dst;
 #pragma unroll
@@ -405,7 +406,8 @@ __device__ __forceinline__ void block_load_rows(const C2<R> *src_, C2<R> *dst, i
     }
     const ITSE_GLOBAL C2<R> *src = gmem(src_);
     constexpr int T = (E + NTH - 1) / NTH;
-    constexpr int TB = 32 / (int)sizeof(C2<R>) * 2;  // loads in flight per batch: 8 (FP32), 4 (FP64)
+    constexpr int TB0 = 64 / (int)sizeof(C2<R>);  // values in 64 bytes: 8 (FP32), 4 (FP64)
+    constexpr int TB = T < 4 * TB0 ? T : 4 * TB0;
 #pragma unroll
     for (int t0 = 0; t0 < T; t0 += TB) {
         C2<R> v[TB];

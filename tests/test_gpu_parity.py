@@ -93,6 +93,21 @@ def test_plain_config_trajectory(itse, orc):
     lat.close()
 
 
+def test_plain_config_reaches_fixed_point(itse):
+    """The 32^3 oscillator run on to 10^4 steps reaches the fixed point of the step
+    map: energy 1.0824349720, the value the oracle tests derive from dense 1D
+    eigensolves of the separable lattice problem (first excited component decays as
+    exp(-1.92 tau), below 1e-10 at tau = 12.5)."""
+    p = synth.config_plain_fp64()
+    lat = itse.Lattice(p.n, p.a, p.mass, p.dtau, kin=p.kin, precision="fp64", center=p.center)
+    lat.set_potential(p.potential_array())
+    lat.set_state(0, p.initial_states()[0])
+    lat.set_options(ortho_every=1, moments=False)
+    lat.step(10000)
+    assert abs(lat.observe(0)["energy"] - 1.0824349720) < 2e-9
+    lat.close()
+
+
 @pytest.mark.parametrize("n,kin,center,parity,ortho", [
     (24, 3, "origin", (1, -1, -1), 1),
     (16, 2, "cell", (0, 0, 0), 1),
