@@ -356,8 +356,9 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=288.0)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only step the 256^3 FP32 workload a few times and profile its passes (for rocprofv3)")
-    ap.add_argument("--form", choices=["precision", "fdtd", "complex"], default="precision",
-                    help="with --kernels-only: the workload (precision), its H_K^(0) form, or one complex state")
+    ap.add_argument("--form", choices=["precision", "fdtd", "complex", "batch"], default="precision",
+                    help="with --kernels-only: the workload (precision), its H_K^(0) form, one complex state, "
+                         "or the 64-lattice batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 256 MiB five times (scale for HBM counters)")
     args = ap.parse_args()
@@ -392,6 +393,9 @@ def main():
         # the timed workload's passes alone, for profilers: a few graph steps, then
         # eager launches of each pass (schedule from --schedule, default 2)
         itse.set_schedule(n, "fp32", args.schedule if args.schedule >= 0 else 2)
+        if args.form == "batch":
+            print(json.dumps({"batch64": batch_leg(torch, itse, 10, 2)}), flush=True)
+            return
         p, v32, st32 = build_workload(n, fp32=True)
         if args.form == "fdtd":
             lat = make_fdtd_lattice(itse, p, v32, st32)

@@ -138,6 +138,15 @@ extern "C" itse_status itse_batch_create(int count, itse_lattice *const *lats, v
         if (!by.count(key)) order.push_back(key);
         by[key].push_back(L);
     }
+    // largest groups first (sites x states): they start first and bound the step
+    auto lat_work = [](const itse_lattice *L) { return (long long)L->d.n * L->d.n * L->d.n * L->d.nstates; };
+    auto group_work = [&](const std::vector<itse_lattice *> &m) {
+        long long w = 0;
+        for (auto *L : m) w += lat_work(L);
+        return w;
+    };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](const auto &x, const auto &y) { return group_work(by[x]) > group_work(by[y]); });
     for (auto &key : order) {
         auto &members = by[key];
         std::vector<JobRef> jobs, lrefs;
