@@ -133,8 +133,9 @@ class Lattice:
         self.close()
 
     @staticmethod
-    def footprint(n, nstates=1, precision="fp64", **kw) -> int:
-        d = _lib.Desc(int(n), 1.0, 1.0, 1e-3, _lib.KIN_NR_CONT, 1, _PREC[precision], 0, int(nstates))
+    def footprint(n, nstates=1, precision="fp64", complex_psi=False, **kw) -> int:
+        d = _lib.Desc(int(n), 1.0, 1.0, 1e-3, _lib.KIN_NR_CONT, 1, _PREC[precision], 0, int(nstates),
+                      1 if complex_psi else 0)
         return int(_lib.load().itse_footprint_bytes(ctypes.byref(d)))
 
     # -- data -----------------------------------------------------------------------------

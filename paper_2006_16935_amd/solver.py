@@ -40,7 +40,9 @@ def run_to_convergence(lat: Lattice, tol: float, relative: bool = False, check_e
     while taken < max_steps:
         lat.step(check_every)
         taken += check_every
-        cur = [o["energy"] for o in lat.observe_all()]
+        # complex lattices: the complex energy (its change in modulus)
+        cur = [complex(o["energy"], o["energy_imag"]) if lat.complex_psi else o["energy"]
+               for o in lat.observe_all()]
         trace.append(cur)
         if prev is not None and converged(prev, cur, tol, relative):
             ok = True

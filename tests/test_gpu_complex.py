@@ -187,11 +187,14 @@ def test_complex_oscillator_ground_state(itse):
     lat.set_potential(v)
     lat.set_state(0, np.exp(-0.5 * r * r).astype(np.complex128))
     lat.set_options(parity=(1,))
-    lat.step(10000)
+    res = itse.run_to_convergence(lat, tol=1e-12, relative=True, check_every=500, max_steps=20000)
+    assert res.converged and isinstance(res.energies[0], complex)
     o = lat.observe(0)
     e = complex(o["energy"], o["energy_imag"])
+    assert e == res.energies[0]
     exact = 1.5 * np.sqrt(2 * c * (1 + 1j) / m)
     assert abs(e - exact) < 5e-3 * abs(exact), (e, exact)
+    assert itse.Lattice.footprint(n, 1, "fp64", complex_psi=True) > itse.Lattice.footprint(n, 2, "fp64")
     lat.close()
 
 
