@@ -276,7 +276,34 @@ def _solve(itse, p, v, states, precision, tol, relative, max_steps, parity):
     return res, lat
 
 
-def study(torch, itse, which: str, max_steps: int):
+def _fixed_solve(itse, p, v, states, precision, steps, parity, chunk=5000):
+    """Run exactly `steps` steps (progress on stderr every `chunk`); returns a result
+    with the energies, the energy change over the last chunk per state, and the
+    lattice."""
+    import types
+    lat = itse.Lattice(p.n, p.a, p.mass, p.dtau, kin=p.kin, subtract_rest_mass=p.subtract_rest_mass,
+                       precision=precision, center=p.center, nstates=len(states))
+    lat.set_potential(v)
+    for i, st in enumerate(states):
+        lat.set_state(i, st)
+    lat.set_options(ortho_every=1, parity=list(parity) if parity else None)
+    t0 = time.perf_counter()
+    prev = None
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        lat.step(k)
+        done += k
+        cur = [o["energy"] for o in lat.observe_all()]
+        if done < steps:
+            prev = cur
+        print(f"study {precision}: {done}/{steps} steps, E = {cur}", file=sys.stderr, flush=True)
+    res = types.SimpleNamespace(energies=cur, steps=done, converged=True, wall_s=time.perf_counter() - t0,
+                                last_change=[abs(a - b) for a, b in zip(cur, prev)] if prev else None)
+    return res, lat
+
+
+def study(torch, itse, which: str, max_steps: int, fixed_steps: int = 0):
     """Converged eigenpairs against the oracle.
 
     precision: the 256^3 precision-form solve (3 states, parity +,-,-) in FP32 (with
@@ -294,12 +321,18 @@ def study(torch, itse, which: str, max_steps: int):
         p = synth.config_precision(256)
         v32 = p.potential_array(np.float64).astype(np.float32)
         s32 = [s.astype(np.float32) for s in p.initial_states()]
-        r32, lat32 = _solve(itse, p, v32, s32, "fp32", p.tol, True, max_steps, p.parity)
+        if fixed_steps:
+            r32, lat32 = _fixed_solve(itse, p, v32, s32, "fp32", fixed_steps, p.parity)
+        else:
+            r32, lat32 = _solve(itse, p, v32, s32, "fp32", p.tol, True, max_steps, p.parity)
         polish = [lat32.polish(i)["energy"] for i in range(p.nstates)]
         st32 = [lat32.get_state(i) for i in range(p.nstates)]
         lat32.close()
-        r64, lat64 = _solve(itse, p, v32.astype(np.float64), [s.astype(np.float64) for s in s32], "fp64",
-                            1e-11, True, max_steps, p.parity)
+        s64 = [s.astype(np.float64) for s in s32]
+        if fixed_steps:
+            r64, lat64 = _fixed_solve(itse, p, v32.astype(np.float64), s64, "fp64", fixed_steps, p.parity)
+        else:
+            r64, lat64 = _solve(itse, p, v32.astype(np.float64), s64, "fp64", 1e-11, True, max_steps, p.parity)
         st64 = [lat64.get_state(i) for i in range(p.nstates)]
         lat64.close()
         L = oracle.lattice(p.n, p.a, p.mass, p.dtau, p.kin, p.subtract_rest_mass, p.center)
@@ -316,6 +349,10 @@ def study(torch, itse, which: str, max_steps: int):
             "relerr_polish": [abs(a - b) / abs(b) for a, b in zip(polish, ref)],
             "relerr_fp64": [abs(a - b) / abs(b) for a, b in zip(r64.energies, ref)],
         })
+        if fixed_steps:
+            out["fixed_steps"] = fixed_steps
+            out["last_chunk_change_fp32"] = r32.last_change
+            out["last_chunk_change_fp64"] = r64.last_change
     else:
         p = synth.config_relativistic_fp64(128)
         v = p.potential_array(np.float64)
@@ -349,6 +386,9 @@ def main():
     ap.add_argument("--study", choices=["precision", "relativistic"], default=None,
                     help="only run a converged-solve study against the oracle and print its JSON line")
     ap.add_argument("--max-steps", type=int, default=60000)
+    ap.add_argument("--fixed-steps", type=int, default=0,
+                    help="with --study precision: run exactly this many steps in each precision "
+                         "instead of stopping on |dE|")
     ap.add_argument("--serving", action="store_true",
                     help="only run the serving form (Poisson arrivals) and print its JSON line")
     ap.add_argument("--requests", type=int, default=24)
@@ -382,7 +422,7 @@ def main():
 
     torch.cuda.set_device(0)
     if args.study:
-        print(json.dumps(study(torch, itse, args.study, args.max_steps)), flush=True)
+        print(json.dumps(study(torch, itse, args.study, args.max_steps, args.fixed_steps)), flush=True)
         return
     if args.serving:
         res = serving_run(torch, itse, args.requests, args.qps, int(args.budget_gb * (1 << 30)))
