@@ -313,6 +313,60 @@ constexpr int VLEN = 16 / (int)sizeof(R);
 template <typename R>
 using Vec = R __attribute__((ext_vector_type(VLEN<R>)));
 
+// Raw loads of lazy_combine: the rows y0 and y1 of every array u_j (j <= i, c_j
+// != 0) over G chunks, all issued before any of them is used.
+template <typename R, int G, int KM>
+struct LazyRaw {
+    Vec<R> v0[KM][G], v1[KM][G];
+};
+
+template <typename R, int G, int KM>
+__device__ __forceinline__ void lazy_issue(const LatView<R, KM> &vw, const size_t (&o0)[G], const size_t (&o1)[G],
+                                           const bool (&ok)[G], LazyRaw<R, G, KM> &raw) {
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        if (j > vw.i || vw.c[j] == 0.0) continue;
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+            if (ok[t]) {
+                raw.v0[j][t] = *(const ITSE_GLOBAL Vec<R> *)(vw.u[j] + o0[t]);
+                raw.v1[j][t] = *(const ITSE_GLOBAL Vec<R> *)(vw.u[j] + o1[t]);
+            }
+        }
+    }
+}
+
+// psi = sum_(j<=i) c_j u_j of the raw loads, in FP64, rounded once.
+template <typename R, int G, int KM>
+__device__ __forceinline__ void lazy_combine(const LatView<R, KM> &vw, const LazyRaw<R, G, KM> &raw,
+                                             R (&p0)[G][VLEN<R>], R (&p1)[G][VLEN<R>]) {
+    constexpr int VL = VLEN<R>;
+    double a0[G][VL], a1[G][VL];
+#pragma unroll
+    for (int t = 0; t < G; ++t)
+#pragma unroll
+        for (int k = 0; k < VL; ++k) a0[t][k] = a1[t][k] = 0.0;
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        if (j > vw.i || vw.c[j] == 0.0) continue;
+        const double c = vw.c[j];
+#pragma unroll
+        for (int t = 0; t < G; ++t)
+#pragma unroll
+            for (int k = 0; k < VL; ++k) {
+                a0[t][k] += c * (double)raw.v0[j][t][k];
+                a1[t][k] += c * (double)raw.v1[j][t][k];
+            }
+    }
+#pragma unroll
+    for (int t = 0; t < G; ++t)
+#pragma unroll
+        for (int k = 0; k < VL; ++k) {
+            p0[t][k] = (R)a0[t][k];
+            p1[t][k] = (R)a1[t][k];
+        }
+}
+
 // Current states of rows y0 and y1 of plane x over G chunks of VLEN consecutive
 // z (chunk t of the calling lane starts at z0[t]): psi = sum_(j<=i) c_j u_j in
 // FP64, rounded once.  All loads of one array are issued before any use.
@@ -883,7 +937,13 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     double acc[NQR];
 #pragma unroll
     for (int q = 0; q < NQR; ++q) acc[q] = 0.0;
-    using PC = PairChunks<R, N, PPW, (MOM || CPX) ? 1 : 2>;
+    // UPFRONT (FP32, no moments, up to four states): every global load of a round (V and
+    // the lazy combination's arrays) is issued before any of them is used, one
+    // memory round trip per round; the registers then allow two chunks per round
+    // for one state and one for more.  Otherwise the arrays load one after another
+    // (each array's loads issued together), two chunks per round without moments.
+    constexpr bool UPFRONT = sizeof(R) == 4 && !MOM && !CPX && KM <= 4;
+    using PC = PairChunks<R, N, PPW, UPFRONT ? (KM > 1 ? 1 : 2) : ((MOM || CPX) ? 1 : 2)>;
     constexpr int VL = PC::VL, GG = PC::G;
     const double cx = site_coord(x, N, center, a);
     // CPX: the real part's raw array and K psi, Im V, the real part's new array
@@ -911,7 +971,7 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
             lp[t] = p * LSZ + z;
         }
         R ph[2][GG][VL];
-        lazy_rows<R, GG>(vw, o0, o1, ok, ph[0], ph[1]);
+        if constexpr (!UPFRONT) lazy_rows<R, GG>(vw, o0, o1, ok, ph[0], ph[1]);
         Vec<R> vv[2][GG];
         Vec<R> xr[2][GG], xk[2][GG], xi[2][GG];  // CPX: u_0, K Re psi, Im V
 #pragma unroll
@@ -928,6 +988,11 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
                     xi[1][t] = *(const ITSE_GLOBAL Vec<R> *)(vic + o1[t]);
                 }
             }
+        if constexpr (UPFRONT) {
+            LazyRaw<R, GG, KM> raw;
+            lazy_issue<R, GG>(vw, o0, o1, ok, raw);
+            lazy_combine<R, GG>(vw, raw, ph[0], ph[1]);
+        }
 #pragma unroll
         for (int t = 0; t < GG; ++t) {
             if (!ok[t]) continue;
