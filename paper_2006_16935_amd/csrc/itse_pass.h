@@ -1474,15 +1474,16 @@ __global__ void __launch_bounds__(NT) k_project_gram_vec(const JobRef *__restric
                 self[t] = xm == x && y == ym;
                 oa[t] = ok[t] ? ((size_t)x * N + y) * N + (size_t)g * VL : 0;
                 ob[t] = ok[t] ? ((size_t)xm * N + ym) * N + (size_t)gb * VL : 0;
+                // unconditional loads (inactive lanes read offset 0, states j >= K
+                // read u_0), the values masked afterwards: straight-line code, so
+                // every load of the round is in flight before the first wait
 #pragma unroll
                 for (int j = 0; j < KM; ++j) {
-                    if (ok[t] && j < K) {
-                        va[t][j] = *(const ITSE_GLOBAL Vec<R> *)(uj[j] + oa[t]);
-                        vb[t][j] = *(const ITSE_GLOBAL Vec<R> *)(uj[j] + ob[t]);
-                    } else {
-                        va[t][j] = Vec<R>{};
-                        vb[t][j] = Vec<R>{};
-                    }
+                    const Vec<R> la = *(const ITSE_GLOBAL Vec<R> *)(uj[j] + oa[t]);
+                    const Vec<R> lb = *(const ITSE_GLOBAL Vec<R> *)(uj[j] + ob[t]);
+                    const bool use = ok[t] && j < K;
+                    va[t][j] = use ? la : Vec<R>{};
+                    vb[t][j] = use ? lb : Vec<R>{};
                 }
             }
 #pragma unroll
