@@ -636,32 +636,31 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
         constexpr int W2 = W / 2;
         constexpr int T = (N * W2 + NTC - 1) / NTC;
         using F4 = float __attribute__((ext_vector_type(4)));
+        // every load unconditional (out-of-range threads and chunks read offset 0),
+        // the values masked where they are used: all loads in flight before the
+        // first wait
         F4 v[T][S];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             const int e = tid + t * NTC;
             const int xx = e / W2, kz = kz0 + 2 * (e % W2);
             const bool ok = ((N * W2) % NTC == 0 || e < N * W2) && kz < H;
-            const size_t base = ((size_t)xx * M + kyp) * HS + kz;
+            const size_t base = ok ? ((size_t)xx * M + kyp) * HS + kz : 0;
 #pragma unroll
-            for (int rr = 0; rr < S; ++rr) {
-                v[t][rr] = ok ? *(const ITSE_GLOBAL F4 *)(spec + rr * sub + base) : F4{0.f, 0.f, 0.f, 0.f};
-                if (kz + 1 >= H) {
-                    v[t][rr].z = 0.f;
-                    v[t][rr].w = 0.f;
-                }
-            }
+            for (int rr = 0; rr < S; ++rr) v[t][rr] = *(const ITSE_GLOBAL F4 *)(spec + rr * sub + base);
         }
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             const int e = tid + t * NTC;
             if ((N * W2) % NTC != 0 && e >= N * W2) continue;
-            const int xx = e / W2, w = 2 * (e % W2);
+            const int xx = e / W2, w = 2 * (e % W2), kz = kz0 + w;
+            // kz >= H: no data; kz + 1 = H: the pair's upper half is row padding
+            const bool oka = kz < H, okb = kz + 1 < H;
             C2<R> a[S], b[S];
 #pragma unroll
             for (int rr = 0; rr < S; ++rr) {
-                a[rr] = C2<R>{v[t][rr].x, v[t][rr].y};
-                b[rr] = C2<R>{v[t][rr].z, v[t][rr].w};
+                a[rr] = oka ? C2<R>{v[t][rr].x, v[t][rr].y} : C2<R>{(R)0, (R)0};
+                b[rr] = okb ? C2<R>{v[t][rr].z, v[t][rr].w} : C2<R>{(R)0, (R)0};
                 if (rr > 0) {
                     a[rr] = cmul(a[rr], tw[rr * kyp]);
                     b[rr] = cmul(b[rr], tw[rr * kyp]);
@@ -674,21 +673,25 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
         }
     } else {
         constexpr int T = (N * W + NTC - 1) / NTC;
+        // unconditional loads (offset 0 when out of range), masked at their use
         C2<R> v[T][S];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             const int e = tid + t * NTC;
             const int xx = e / W, kz = kz0 + e % W;
             const bool ok = ((N * W) % NTC == 0 || e < N * W) && kz < H;
-            const size_t base = ((size_t)xx * M + kyp) * HS + kz;
+            const size_t base = ok ? ((size_t)xx * M + kyp) * HS + kz : 0;
 #pragma unroll
-            for (int rr = 0; rr < S; ++rr) v[t][rr] = ok ? spec[rr * sub + base] : C2<R>{(R)0, (R)0};
+            for (int rr = 0; rr < S; ++rr) v[t][rr] = spec[rr * sub + base];
         }
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             const int e = tid + t * NTC;
             if ((N * W) % NTC != 0 && e >= N * W) continue;
             const int xx = e / W, w = e % W;
+            if (kz0 + w >= H)
+#pragma unroll
+                for (int rr = 0; rr < S; ++rr) v[t][rr] = C2<R>{(R)0, (R)0};
 #pragma unroll
             for (int rr = 1; rr < S; ++rr) v[t][rr] = cmul(v[t][rr], tw[rr * kyp]);
             Dft<S, -1, R>::run(v[t]);
@@ -942,7 +945,7 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     // memory round trip per round; the registers then allow two chunks per round
     // for one state and one for more.  Otherwise the arrays load one after another
     // (each array's loads issued together), two chunks per round without moments.
-    constexpr bool UPFRONT = sizeof(R) == 4 && !MOM && !CPX && KM <= 4;
+    constexpr bool UPFRONT = (sizeof(R) == 4 || N >= 128) && !MOM && !CPX && KM <= 4;
     using PC = PairChunks<R, N, PPW, UPFRONT ? (KM > 1 ? 1 : 2) : ((MOM || CPX) ? 1 : 2)>;
     constexpr int VL = PC::VL, GG = PC::G;
     const double cx = site_coord(x, N, center, a);
