@@ -56,7 +56,8 @@ def pass_bytes(n: int, w: int, nstates: int, parity, ortho: bool, axes=None):
 def measured_traffic(kernel: str, variant: int):
     """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, scaled by a plain
     copy) from the committed counter summary of the 256^3 FP32 three-state step, if
-    it was taken with this schedule variant from the current kernel sources."""
+    it holds a record for this schedule variant taken from the current kernel
+    sources."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     try:
@@ -67,13 +68,15 @@ def measured_traffic(kernel: str, variant: int):
     for ln in lines:
         if ln.startswith("traffic-json: "):
             rec = json.loads(ln[len("traffic-json: "):])
-    if not rec or rec.get("kernel") != kernel or rec.get("variant") != variant:
+    per_variant = (rec or {}).get("bytes")
+    got = per_variant.get(str(variant), {}).get(kernel) if isinstance(per_variant, dict) else None
+    if got is None:
         return None
     h = hashlib.sha256()
     for name in ("itse_pass.h", "itse_fft.h", "itse_launch.h", "itse_internal.h"):
         with open(os.path.join(root, "paper_2006_16935_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
-    return rec["bytes"] if h.hexdigest() == rec["sources_sha256"] else None
+    return got if h.hexdigest() == rec["sources_sha256"] else None
 
 
 def build_workload(n: int, fp32: bool):
