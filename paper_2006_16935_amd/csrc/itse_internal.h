@@ -77,7 +77,6 @@ struct LatDev {
     double coef[MAXK][MAXK];  // current state i = sum_j coef[j][i] u[j]
     long long step;
     int error;                // bit0 non-finite, bit1 Gram not positive definite, bit2 unstable V
-    int fin_count;            // finalisation workgroups done this step (reset by the last)
     double fin_sums[MAXK * (NQR + NQC) + MAXK * (MAXK + 1) / 2];
     ObsDev obs[MAXK];
     ObsDev *hist;             // [HIST_CAP][MAXK]

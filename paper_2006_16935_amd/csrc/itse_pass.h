@@ -940,11 +940,12 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     double acc[NQR];
 #pragma unroll
     for (int q = 0; q < NQR; ++q) acc[q] = 0.0;
-    // UPFRONT (FP32, no moments, up to four states): every global load of a round (V and
-    // the lazy combination's arrays) is issued before any of them is used, one
-    // memory round trip per round; the registers then allow two chunks per round
-    // for one state and one for more.  Otherwise the arrays load one after another
-    // (each array's loads issued together), two chunks per round without moments.
+    // UPFRONT (FP32 lattices and FP64 from N = 128; no moments, no complex part, up to
+    // four states): every global load of a round (V and the lazy combination's
+    // arrays) is issued before any of them is used, one memory round trip per round;
+    // the registers then allow two chunks per round for one state and one for more.
+    // Otherwise the arrays load one after another (each array's loads issued
+    // together), two chunks per round without moments.
     constexpr bool UPFRONT = (sizeof(R) == 4 || N >= 128) && !MOM && !CPX && KM <= 4;
     using PC = PairChunks<R, N, PPW, UPFRONT ? (KM > 1 ? 1 : 2) : ((MOM || CPX) ? 1 : 2)>;
     constexpr int VL = PC::VL, GG = PC::G;
