@@ -415,9 +415,8 @@ def main():
         print(json.dumps({"copy_bytes_each_way": x.numel() * 4, "copies": 5}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs one lattice per GPU on a single GPU; "
-                                   "--gpus must be 1 (multi-GPU sharding is described in DESIGN.md, "
-                                   "not implemented)"}))
+        print(json.dumps({"error": "the step runs on one GPU (each lattice lives whole on one GPU; "
+                                   "no sharding across GPUs is implemented): --gpus must be 1"}))
         sys.exit(2)
 
     import torch

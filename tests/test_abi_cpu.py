@@ -57,7 +57,7 @@ def _create(**kw):
 @pytest.mark.parametrize("kw,status", [
     (dict(n=20), -1),            # factor 5
     (dict(n=4), -1),             # too small
-    (dict(n=1024), -1),          # too large for this build
+    (dict(n=1024), -1),          # above the largest supported N (256)
     (dict(a=0.0), -1),
     (dict(mass=-1.0), -1),
     (dict(kin=7), -1),
