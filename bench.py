@@ -138,7 +138,7 @@ def timed_steps(torch, lat, steps: int, warmup: int):
     return start.elapsed_time(stop) / 1000.0
 
 
-def cpu_baseline(p, v, states, target_s: float = 10.0, max_steps: int = 50):
+def cpu_baseline(p, v, states, target_s: float = 14.0, max_steps: int = 50):
     """The FP64 oracle on the same 256^3 workload: one untimed step of all states,
     then as many steps as fill about target_s seconds (at most max_steps), timed."""
     import oracle
