@@ -405,9 +405,9 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=288.0)
     ap.add_argument("--kernels-only", action="store_true",
                     help="only step the 256^3 FP32 workload a few times and profile its passes (for rocprofv3)")
-    ap.add_argument("--form", choices=["precision", "fdtd", "complex", "batch"], default="precision",
+    ap.add_argument("--form", choices=["precision", "fdtd", "complex", "batch", "fp64"], default="precision",
                     help="with --kernels-only: the workload (precision), its H_K^(0) form, one complex state, "
-                         "or the 64-lattice batch")
+                         "the 64-lattice batch, or the workload in FP64 (schedule default 1)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 256 MiB five times (scale for HBM counters)")
     args = ap.parse_args()
@@ -443,6 +443,15 @@ def main():
         itse.set_schedule(n, "fp32", args.schedule if args.schedule >= 0 else 2)
         if args.form == "batch":
             print(json.dumps({"batch64": batch_leg(torch, itse, 10, 2)}), flush=True)
+            return
+        if args.form == "fp64":
+            itse.set_schedule(n, "fp64", args.schedule if args.schedule >= 0 else 1)
+            p, v64, st64 = build_workload(n, fp32=False)
+            lat = make_lattice(itse, p, v64, st64, fp32=False)
+            lat.step(2)
+            prof = lat.profile_step(args.profile_steps)
+            lat.close()
+            print(json.dumps({"passes_ms": prof}), flush=True)
             return
         p, v32, st32 = build_workload(n, fp32=True)
         if args.form == "fdtd":
