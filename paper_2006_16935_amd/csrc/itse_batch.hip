@@ -301,18 +301,19 @@ static itse_status time_variant(int n, int precision, int v, int nstates, void *
     const int reps = n >= 192 ? 10 : 30;
     float ms = 1e30f;
     for (int trial = 0; trial < 2 && !st; ++trial) {
-        hipEvent_t e0, e1;
-        (void)hipEventCreate(&e0);
-        (void)hipEventCreate(&e1);
-        (void)hipEventRecord(e0, (hipStream_t)stream);
-        st = itse_step(L, reps, nullptr);
-        (void)hipEventRecord(e1, (hipStream_t)stream);
-        (void)hipEventSynchronize(e1);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t he = hipEventCreate(&e0);
+        if (he == hipSuccess) he = hipEventCreate(&e1);
+        if (he == hipSuccess) he = hipEventRecord(e0, (hipStream_t)stream);
+        if (he == hipSuccess) st = itse_step(L, reps, nullptr);
+        if (he == hipSuccess && !st) he = hipEventRecord(e1, (hipStream_t)stream);
+        if (he == hipSuccess && !st) he = hipEventSynchronize(e1);
         float t = 0.f;
-        (void)hipEventElapsedTime(&t, e0, e1);
-        ms = std::min(ms, t);
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
+        if (he == hipSuccess && !st) he = hipEventElapsedTime(&t, e0, e1);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (he != hipSuccess && !st) st = fail(ITSE_EDEVICE, "autotune timing: %s", hipGetErrorString(he));
+        if (!st) ms = std::min(ms, t);
     }
     if (!st) st = itse_sync(L);
     itse_destroy(L);

@@ -917,19 +917,23 @@ itse_status capture_steps(hipStream_t cap, const std::vector<Group> &groups, int
         for (int s = 0; s < nsteps && err == hipSuccess; ++s) err = enqueue_step(groups[0], cap);
     } else {
         // fork: each group on its own branch stream, joined at the end
-        hipEvent_t fork;
-        (void)hipEventCreateWithFlags(&fork, hipEventDisableTiming);
-        evs.push_back(fork);
-        (void)hipEventRecord(fork, cap);
+        hipEvent_t fork = nullptr;
+        err = hipEventCreateWithFlags(&fork, hipEventDisableTiming);
+        if (err == hipSuccess) {
+            evs.push_back(fork);
+            err = hipEventRecord(fork, cap);
+        }
         for (size_t g = 0; g < groups.size() && err == hipSuccess; ++g) {
             hipStream_t bs = branch[g % branch.size()];
-            (void)hipStreamWaitEvent(bs, fork, 0);
+            err = hipStreamWaitEvent(bs, fork, 0);
             for (int s = 0; s < nsteps && err == hipSuccess; ++s) err = enqueue_step(groups[g], bs);
-            hipEvent_t join;
-            (void)hipEventCreateWithFlags(&join, hipEventDisableTiming);
-            evs.push_back(join);
-            (void)hipEventRecord(join, bs);
-            (void)hipStreamWaitEvent(cap, join, 0);
+            hipEvent_t join = nullptr;
+            if (err == hipSuccess) err = hipEventCreateWithFlags(&join, hipEventDisableTiming);
+            if (err == hipSuccess) {
+                evs.push_back(join);
+                err = hipEventRecord(join, bs);
+            }
+            if (err == hipSuccess) err = hipStreamWaitEvent(cap, join, 0);
         }
     }
     hipGraph_t graph = nullptr;
