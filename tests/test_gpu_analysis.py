@@ -71,3 +71,32 @@ def test_analysis_rejects_bad_arguments(itse):
     with pytest.raises(itse.ItseError):
         lat.momentum_radial(0, 513)
     lat.close()
+
+
+def test_hydrogen_box_radii(itse, orc):
+    """itse_analyse on the analytic hydrogen 1s, 2s and 2p states sampled on a 64^3
+    FP64 lattice (M = 0.3 GeV, A = 0.12 fm, min_sep_edge = 0.3, centred on a
+    site): the box radii the paper prints, 8.14, 20.30 and 19.06 (to their last
+    digit), and the oracle's analysis of the same arrays to 1e-12."""
+    g = {}
+    import os
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "hydrogen_box_radii.txt")):
+        f = line.split("#", 1)[0].split()
+        if len(f) == 2:
+            g[f[0]] = float(f[1])
+    n = 64
+    a = g["A_fm"] / g["hbar_c_GeV_fm"]
+    m = g["M_GeV"]
+    lat = itse.Lattice(n, a, m, a * a * m / 8, kin=1, precision="fp64", center="origin", nstates=3)
+    x = synth.axis_coords(n, a, "origin")
+    r = np.sqrt(x[:, None, None] ** 2 + x[None, :, None] ** 2 + x[None, None, :] ** 2)
+    zr = np.where(r > 0, x[None, None, :] / np.where(r > 0, r, 1.0), 0.0)
+    states = {"1s": np.exp(-m * r), "2s": (2 - m * r) * np.exp(-m * r / 2), "2p": m * r * np.exp(-m * r / 2) * zr}
+    for i, psi in enumerate(states.values()):
+        lat.set_state(i, psi)
+    for i, (name, psi) in enumerate(states.items()):
+        got = lat.analyse(i, g["min_sep_edge"])
+        ref = orc.analyse(_olat(orc, lat), lat.get_state(i), g["min_sep_edge"])
+        assert abs(got["rho_box"] - ref["rho_box"]) <= 1e-12 * ref["rho_box"], name
+        assert abs(got["rho_box"] - g[f"rho_box_{name}_N64"]) <= 0.005, (name, got["rho_box"])
+    lat.close()

@@ -72,3 +72,58 @@ def test_momentum_radial_plane_wave(orc):
     assert abs(out["p"][1] - dp * (6 + 12 * np.sqrt(2)) / 18) < 1e-12
     assert abs(out["y"][1] - np.sqrt(4 * np.pi) * out["p"][1] * out["psi"][1]) < 1e-12
     assert np.abs(out["psi"][np.arange(12) != 1]).max() < 1e-10
+
+
+# ---------------------------------------------------------------------------------
+# The paper's printed box radii of the analytic hydrogen states
+# ---------------------------------------------------------------------------------
+def _golden_radii():
+    import os
+    vals = {}
+    path = os.path.join(os.path.dirname(__file__), "golden", "hydrogen_box_radii.txt")
+    for line in open(path):
+        line = line.split("#", 1)[0].split()
+        if len(line) == 2:
+            vals[line[0]] = float(line[1])
+    return vals
+
+
+def _hydrogen(n, a, center, mass):
+    """The continuum 1s, 2s and 2p (angular factor z / r) states sampled on the
+    lattice sites about the centre (equation of the analytic hydrogen states in
+    section "Comparison between the different non-relativistic kinetic terms")."""
+    x, y, z = _grid(n, a, center)
+    r = np.sqrt(x * x + y * y + z * z)
+    ang = np.where(r > 0, z / np.where(r > 0, r, 1.0), 0.0)
+    return {"1s": np.exp(-mass * r), "2s": (2.0 - mass * r) * np.exp(-mass * r / 2.0),
+            "2p": mass * r * np.exp(-mass * r / 2.0) * ang}
+
+
+@pytest.mark.parametrize("n,center,tol", [(64, "origin", 0.005), (128, "cell", 0.01)])
+def test_box_radii_of_hydrogen_states(orc, n, center, tol):
+    """rho_box of the analytic hydrogen states in the effective volume of
+    min_sep_edge = 0.3 against the radii the paper prints for them (M = 0.3 GeV,
+    A = 0.12 fm).  At N = 64 the printed values are reproduced to their last digit
+    by sampling about a lattice site (integer coordinates, |c| <= 22 in each axis);
+    at N = 128 by sampling about the cell centre (half-integer coordinates,
+    |c| <= 44.5), within one unit of the last printed digit.  A box one site wider
+    or narrower, a radius not divided by A or a norm taken over the full lattice
+    moves at least one of them by more than that."""
+    g = _golden_radii()
+    a = g["A_fm"] / g["hbar_c_GeV_fm"]
+    L = orc.lattice(n, a, g["M_GeV"], center=center)
+    for name, psi in _hydrogen(n, a, center, g["M_GeV"]).items():
+        got = orc.analyse(L, psi, g["min_sep_edge"])["rho_box"]
+        assert abs(got - g[f"rho_box_{name}_N{n}"]) <= tol, (name, got)
+
+
+def test_infinite_volume_radii_of_hydrogen_states():
+    """The continuum radii 3/(2M), 6/M and 5/M in units of A (equation of the
+    analytic average radii) against the printed 8.21, 32.83 and 27.36: they agree
+    to 0.2 % (the printed values imply hbar c = 0.197 GeV fm), which fixes the unit
+    conversion A = 0.12 fm / (hbar c) used above."""
+    g = _golden_radii()
+    a = g["A_fm"] / g["hbar_c_GeV_fm"]
+    m = g["M_GeV"]
+    for name, r in (("1s", 1.5 / m), ("2s", 6.0 / m), ("2p", 5.0 / m)):
+        assert abs(r / a / g[f"rho_inf_{name}"] - 1.0) <= 2.5e-3, name
