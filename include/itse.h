@@ -71,7 +71,8 @@ typedef enum {
 typedef enum {
     ITSE_FP64 = 0,         /* FP64 storage, transforms and sums                    */
     ITSE_FP32 = 1          /* FP32 storage and transforms, FP64 sums and Gram-     */
-                           /* Schmidt coefficients, FP64 kinetic symbol            */
+                           /* Schmidt coefficients; the kinetic symbol T(k) is    */
+                           /* evaluated in FP64 and rounded once to FP32          */
 } itse_precision;
 
 typedef enum {
@@ -203,7 +204,11 @@ long long itse_step_count(const itse_lattice *lat);
  * itse_momentum_radial, itse_snapshot_push, itse_snapshot_extract; and the
  * server takes real states only. */
 
-/* Modified Gram-Schmidt of state i against states 0..i-1, then normalise. */
+/* Modified Gram-Schmidt of state i against states 0..i-1, then normalise: the
+ * removal of the components along the lower states by which excited states are
+ * extracted, and the full-volume normalisation sum |psi|^2 = 1 (section "The
+ * iterative procedure").  Errors: ITSE_EINVAL (index), ITSE_ENONFINITE (state i in
+ * the span of the lower states), ITSE_ESTATE (complex lattice).  Synchronises. */
 itse_status itse_orthogonalise(itse_lattice *lat, int i);
 
 /* P psi_i = (psi_i + sign * psi_i o R)/2 with R reflecting `axes`, then

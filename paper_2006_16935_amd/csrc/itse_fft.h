@@ -34,6 +34,36 @@ __device__ __forceinline__ C2<R> mul_si(C2<R> a) {
     return SIGN > 0 ? C2<R>{-a.y, a.x} : C2<R>{a.y, -a.x};
 }
 
+// The rotation constants of the FP32 butterflies (cos and sin of multiples of
+// pi/8 and pi/6) are carried as unevaluated sums hi + lo of two floats (hi the
+// float nearest to the value, lo the float nearest to the rest).  With one float
+// per constant the rotations would not be unitary, in a systematic way: the floats
+// nearest to cos(pi/8), sin(pi/8), sqrt(1/2) and sqrt(3)/2 all lie below those
+// values, so every radix-8, -12 and -16 butterfly would shrink the modes it
+// rotates (by about 5e-8 per transform at N = 256), and the kinetic energy
+// <psi|H_K psi> formed through the transforms would come out low by a few 1e-7
+// relative.  a (hi + lo) = a hi + a lo costs one rounding more than a plain
+// product and carries no such bias.  The twiddle tables hold one float pair per
+// entry, chosen among the neighbours of (cos, sin) for the magnitude closest to 1
+// (see the table set-up).  FP64 transforms use one double per constant (their
+// bias is at the 1e-16 level).
+
+// a * (w + wl) in FP32: the low part's product first, then the high part's, fused.
+__device__ __forceinline__ C2<float> cmul2(C2<float> a, C2<float> w, C2<float> wl) {
+    const float lr = a.x * wl.x - a.y * wl.y;
+    const float li = a.x * wl.y + a.y * wl.x;
+    return {__builtin_fmaf(a.x, w.x, __builtin_fmaf(-a.y, w.y, lr)),
+            __builtin_fmaf(a.x, w.y, __builtin_fmaf(a.y, w.x, li))};
+}
+
+// a times table twiddle e, conjugated for SIGN > 0.
+template <int SIGN, typename R>
+__device__ __forceinline__ C2<R> tw_mul(C2<R> a, const C2<R> *tw, int e) {
+    C2<R> w = tw[e];
+    if (SIGN > 0) w.y = -w.y;
+    return cmul(a, w);
+}
+
 // cos(2 pi e / R) for R in {16, 12} (R = 8, 6, 4, 3, 2 map onto these).  The
 // values are the exact trigonometric constants rounded to double.
 __host__ __device__ constexpr double unit_cos(int R, int e) {
@@ -77,9 +107,15 @@ __device__ __forceinline__ C2<T> twiddle_c(C2<T> a) {
         constexpr int RR = (R == 6) ? 12 : R;
         constexpr int EE = (R == 6) ? 2 * e : e;
         constexpr double c = unit_cos(RR, EE);
-        constexpr double s = unit_cos(RR, EE - RR / 4);
-        const C2<T> w{(T)c, (T)(SIGN * s)};
-        return cmul(a, w);
+        constexpr double s = SIGN * unit_cos(RR, EE - RR / 4);
+        if constexpr (sizeof(T) == 4) {
+            constexpr float ch = (float)c, sh = (float)s;
+            constexpr float cl = (float)(c - (double)ch), sl = (float)(s - (double)sh);
+            return cmul2(a, C2<T>{ch, sh}, C2<T>{cl, sl});
+        } else {
+            const C2<T> w{(T)c, (T)s};
+            return cmul(a, w);
+        }
     }
 }
 
@@ -107,11 +143,18 @@ template <int SIGN, typename T>
 struct Dft<3, SIGN, T> {
     static __device__ __forceinline__ void run(C2<T> *a) {
         // w = exp(SIGN 2 pi i / 3) = -1/2 + SIGN i sqrt(3)/2
-        const T hs3 = (T)0.86602540378443864676;
+        constexpr double hs3 = 0.86602540378443864676;
         const C2<T> t1 = cadd(a[1], a[2]);
         const C2<T> t2 = {a[0].x - (T)0.5 * t1.x, a[0].y - (T)0.5 * t1.y};
         const C2<T> d = csub(a[1], a[2]);
-        const C2<T> r = mul_si<SIGN>(C2<T>{hs3 * d.x, hs3 * d.y});
+        C2<T> hd;
+        if constexpr (sizeof(T) == 4) {
+            constexpr float hh = (float)hs3, hl = (float)(hs3 - (double)hh);
+            hd = C2<T>{__builtin_fmaf(hh, d.x, hl * d.x), __builtin_fmaf(hh, d.y, hl * d.y)};
+        } else {
+            hd = C2<T>{(T)hs3 * d.x, (T)hs3 * d.y};
+        }
+        const C2<T> r = mul_si<SIGN>(hd);
         a[0] = cadd(a[0], t1);
         a[1] = cadd(t2, r);
         a[2] = csub(t2, r);
@@ -265,11 +308,7 @@ __device__ __forceinline__ void wave_stage(C2<R> *__restrict__ buf, int LS, int 
 #pragma unroll
             for (int m = 0; m < RAD; ++m) {
                 C2<R> a = b[padded<MR, G>(j + m * B) * ES];
-                if (P > 1 && m > 0) {
-                    C2<R> w = tw[(k * m * (L / (P * RAD))) * TWS];
-                    if (SIGN > 0) w.y = -w.y;
-                    a = cmul(a, w);
-                }
+                if (P > 1 && m > 0) a = tw_mul<SIGN>(a, tw, (k * m * (L / (P * RAD))) * TWS);
                 v[t][m] = a;
             }
             Dft<RAD, SIGN, R>::run(v[t]);
@@ -349,7 +388,7 @@ struct WaveFftPair {
 #pragma unroll
                 for (int m = 0; m < G; ++m) {
                     C2<R> a = b[padded<MODE, G>(j + m * B) * ES];
-                    if (m > 0) a = cmul(a, tw[(j * m) * TWS]);
+                    if (m > 0) a = tw_mul<-1>(a, tw, (j * m) * TWS);
                     v[t][m] = a;
                 }
                 Dft<G, -1, R>::run(v[t]);

@@ -11,8 +11,9 @@
 //                        complex FFT of length M = N/S along j.
 //   P2 (columns)         for (y', kz-chunk): radix-S combination of the S
 //                        sub-spectra (completing the y transform), FFT along x,
-//                        multiply by T(k)/N^3 (FP64 symbol and product), inverse
-//                        FFT along x, inverse radix-S split.
+//                        multiply by T(k)/N^3 (symbol evaluated in FP64 and rounded
+//                        once to the lattice precision), inverse FFT along x,
+//                        inverse radix-S split.
 //   P3 (plane, inverse)  length-M inverse FFT along j, C2R along z, then the
 //                        update and FP64 partial sums of <psi|psi>, <psi|K psi>,
 //                        <psi|V psi>, <psi'|psi'> (and moments).
@@ -197,19 +198,31 @@ __device__ __forceinline__ int mirror_idx(int idx, int n, int center) {
 enum SymKind { SYM_SUM = 0, SYM_REL = 1, SYM_REL_SUB = 2 };
 
 // T / N^3 for the table sum s.  FP64 lattices: correctly rounded FP64 operations.
-// FP32 lattices: the FP32 value of s with the hardware reciprocal square root and
-// reciprocal (a few ulps of FP32, the level of the transforms' own rounding).
+// FP32 lattices: T evaluated in FP64 and rounded once to FP32.  The square root
+// and the reciprocal start from the FP32 hardware estimates (about 1e-7 relative)
+// and take one Newton-Raphson step in FP64 (y <- y (3 - x y^2)/2 for x^-1/2,
+// q <- q (2 - d q) for 1/d), which squares the relative error to ~1e-14, far
+// below FP32's half ulp; T then carries only the one rounding to FP32, with no
+// bias from the estimates (an error in T enters the energy at first order).
 template <typename R, int KIND>
 __device__ __forceinline__ R symbol_scaled(double s, double mass, double inv_n3) {
     if constexpr (sizeof(R) == 4) {
-        const float sf = (float)s, m = (float)mass;
-        float t = sf;
+        double t = s;
         if constexpr (KIND != SYM_SUM) {
-            const float x = sf + m * m;
-            const float e = x * __builtin_amdgcn_rsqf(x);
-            t = KIND == SYM_REL ? e : sf * __builtin_amdgcn_rcpf(e + m);
+            const double x = s + mass * mass;
+            double y = (double)__builtin_amdgcn_rsqf((float)x);
+            y = y * (1.5 - 0.5 * x * y * y);
+            const double e = x * y;
+            if constexpr (KIND == SYM_REL) {
+                t = e;
+            } else {
+                const double d = e + mass;
+                double q = (double)__builtin_amdgcn_rcpf((float)d);
+                q = q * (2.0 - d * q);
+                t = s * q;
+            }
         }
-        return t * (float)inv_n3;
+        return (R)(t * inv_n3);
     } else {
         double t = s;
         if constexpr (KIND != SYM_SUM) {
@@ -662,8 +675,8 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
                 a[rr] = oka ? C2<R>{v[t][rr].x, v[t][rr].y} : C2<R>{(R)0, (R)0};
                 b[rr] = okb ? C2<R>{v[t][rr].z, v[t][rr].w} : C2<R>{(R)0, (R)0};
                 if (rr > 0) {
-                    a[rr] = cmul(a[rr], tw[rr * kyp]);
-                    b[rr] = cmul(b[rr], tw[rr * kyp]);
+                    a[rr] = tw_mul<-1>(a[rr], tw, rr * kyp);
+                    b[rr] = tw_mul<-1>(b[rr], tw, rr * kyp);
                 }
             }
             Dft<S, -1, R>::run(a);
@@ -693,7 +706,7 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
 #pragma unroll
                 for (int rr = 0; rr < S; ++rr) v[t][rr] = C2<R>{(R)0, (R)0};
 #pragma unroll
-            for (int rr = 1; rr < S; ++rr) v[t][rr] = cmul(v[t][rr], tw[rr * kyp]);
+            for (int rr = 1; rr < S; ++rr) v[t][rr] = tw_mul<-1>(v[t][rr], tw, rr * kyp);
             Dft<S, -1, R>::run(v[t]);
 #pragma unroll
             for (int q = 0; q < S; ++q) buf[xx * CS + q * W + w] = v[t][q];
@@ -832,8 +845,8 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
             for (int rr = 0; rr < S; ++rr) {
                 C2<R> x0 = a[rr], x1 = b[rr];
                 if (rr > 0) {
-                    x0 = cmul(x0, cconj(tw[rr * kyp]));
-                    x1 = cmul(x1, cconj(tw[rr * kyp]));
+                    x0 = tw_mul<+1>(x0, tw, rr * kyp);
+                    x1 = tw_mul<+1>(x1, tw, rr * kyp);
                 }
                 if (kz + 1 < H) *(ITSE_GLOBAL F4 *)(spec + rr * sub + base) = F4{x0.x, x0.y, x1.x, x1.y};
                 else spec[rr * sub + base] = x0;
@@ -852,7 +865,7 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
 #pragma unroll
         for (int rr = 0; rr < S; ++rr) {
             C2<R> a = v[rr];
-            if (rr > 0) a = cmul(a, cconj(tw[rr * kyp]));
+            if (rr > 0) a = tw_mul<+1>(a, tw, rr * kyp);
             spec[rr * sub + base] = a;
         }
     }

@@ -5,12 +5,13 @@ radial momentum-space wave-function.
 
 Tolerances: the analysis sums are FP64 over the same stored values, 1e-12 relative
 (order of summation); the momentum-space values come from the lattice's own
-transform, 1e-12 relative for FP64 lattices and 1e-5 for FP32 lattices (one FP32
-transform)."""
+transform, 1e-12 relative for FP64 lattices and, for FP32 lattices (one FP32
+transform), about four times the largest error measured on an MI355X."""
 import numpy as np
 import pytest
 
 import synth
+from measure import check
 
 pytestmark = pytest.mark.gpu
 
@@ -54,9 +55,12 @@ def test_momentum_radial_matches_oracle(itse, orc, n, prec, center):
     got = lat.momentum_radial(0, nb)
     ref = orc.momentum_radial(_olat(orc, lat), lat.get_state(0), nb)
     assert np.array_equal(got["count"], ref["count"])
-    tol = 1e-12 if prec == "fp64" else 1e-5
     for k in ("p", "psi", "y"):
-        assert np.abs(got[k] - ref[k]).max() <= tol * np.abs(ref[k]).max(), k
+        err = np.abs(got[k] - ref[k]).max() / np.abs(ref[k]).max()
+        if prec == "fp64":
+            assert err <= 1e-12, k
+        else:
+            check(f"analysis.momentum_radial[{n}].{k}", err, {"p": 2e-13, "psi": 2e-7, "y": 8e-8}[k])
     lat.close()
 
 

@@ -2,13 +2,15 @@
 per chunk of steps) and of the serving loop (admission by HBM footprint,
 continuous batching), through the C ABI, against the FP64 oracle.
 
-Tolerances: FP32 lattices, 1e-5 relative on step energies against the oracle on
-the same FP32 inputs; batched against alone: bitwise.  Converged eigenpairs are
+Tolerances: FP32 lattices, step energies against the oracle on the same FP32
+inputs within about four times the largest error measured on an MI355X (printed
+by each run, see measure.py); batched against alone: bitwise.  Converged eigenpairs are
 certified by the oracle's residual of the step map."""
 import numpy as np
 import pytest
 
 import synth
+from measure import check, max_rel_energy
 
 pytestmark = pytest.mark.gpu
 
@@ -55,10 +57,7 @@ def test_batched_mix_matches_oracle_and_alone(itse, orc):
         states = [s.astype(np.float32).astype(np.float64) for s in p.initial_states()]
         _, oh = orc.step(_olat(orc, p), states, v, steps)
         hb = mixed[j].history(steps)
-        for s in range(steps):
-            for i in range(p.nstates):
-                g, r = hb[s][i]["energy"], oh[s][i]["energy"]
-                assert abs(g - r) <= 1e-5 * abs(r), (j, s, i, g, r)
+        check(f"batch.mix_energies[{j}]", max_rel_energy(hb, oh), 2.5e-7)
     batch.close()
     for lat in alone + mixed:
         lat.close()

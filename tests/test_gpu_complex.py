@@ -8,13 +8,15 @@ passes write K Re psi and K Im psi, one update kernel forms
 reports one observable record with energy_imag = <psi|Vi psi>/<psi|psi>.
 
 Tolerances: FP64 lattices 1e-10 relative on energies and 1e-10 of the largest
-value on states; FP32 lattices (FP32 storage and transforms, FP64 sums) 1e-5 and
-1e-4, as for real states.  Energies are compared with max(1, |E|) scaling
-(energy_imag can be small)."""
+value on states; FP32 lattices (FP32 storage and transforms, FP64 sums) about four
+times the largest error measured on an MI355X (printed by each run, see
+measure.py).  Energies are compared with max(1, |E|) scaling (energy_imag can be
+small)."""
 import numpy as np
 import pytest
 
 import synth
+from measure import check
 
 pytestmark = pytest.mark.gpu
 
@@ -71,20 +73,22 @@ def test_complex_steps(itse, orc, n, prec, kin, center, parity, moments):
     hist = lat.history(steps)
     ostate, ohist = orc.step_complex(_olat(orc, lat), psi.astype(np.complex128), v.astype(np.complex128), steps,
                                      parity=parity, axes=7, moments=moments)
-    etol = 1e-10 if prec == "fp64" else 1e-5
     fields = FIELDS + (MOMENTS if moments else ())
     if kin == 0:
         fields = tuple(f for f in fields if f != "parity_even")  # not formed by H_K^(0) steps
-    for s in range(steps):
-        for f in fields:
-            g, r = hist[s][0][f], ohist[s][f]
-            assert abs(g - r) <= etol * max(1.0, abs(r)), (s, f, g, r)
-        if kin == 0:
-            assert hist[s][0]["parity_even"] == -1.0
+    e = max(abs(hist[s][0][f] - ohist[s][f]) / max(1.0, abs(ohist[s][f])) for s in range(steps) for f in fields)
+    if kin == 0:
+        assert all(hist[s][0]["parity_even"] == -1.0 for s in range(steps))
     got = lat.get_state(0)
     assert np.iscomplexobj(got)
-    assert _rel(got, ostate) < (1e-10 if prec == "fp64" else 1e-4)
-    assert abs(np.sum(np.abs(got) ** 2) - 1.0) < (1e-12 if prec == "fp64" else 1e-5)
+    st = _rel(got, ostate)
+    nerr = abs(np.sum(np.abs(got) ** 2) - 1.0)
+    if prec == "fp64":
+        assert e <= 1e-10 and st <= 1e-10 and nerr < 1e-12, (e, st, nerr)
+    else:
+        check(f"complex.steps[{n},{kin},{center}].energies", e, 2.2e-7)
+        check(f"complex.steps[{n},{kin},{center}].state", st, 2.7e-6)
+        check(f"complex.steps[{n},{kin},{center}].norm", nerr, 1.6e-9)
     lat.close()
 
 
@@ -119,8 +123,8 @@ def test_complex_kinetic_parts(itse, orc):
 
 def test_complex_large_first_steps(itse, orc):
     """256^3 FP32, relativistic lattice kinetic term, complex oscillator potential:
-    the first steps' complex energies match the FP64 oracle on the same FP32 inputs;
-    sampled sites of the state after them too."""
+    the first steps' complex energies match the FP64 oracle on the same FP32 inputs,
+    and the whole state after them, site by site."""
     n, a = 256, 0.05
     lat = _lat(itse, n, "fp32", 3, a=a, mass=1.3, center="origin")
     v, psi = _inputs(n, a, "origin", "fp32", 11)
@@ -129,14 +133,10 @@ def test_complex_large_first_steps(itse, orc):
     lat.step(2)
     hist = lat.history(2)
     ostate, ohist = orc.step_complex(_olat(orc, lat), psi.astype(np.complex128), v.astype(np.complex128), 2)
-    for s in range(2):
-        for f in ("energy", "energy_imag", "kinetic", "potential"):
-            g, r = hist[s][0][f], ohist[s][f]
-            assert abs(g - r) <= 1e-5 * max(1.0, abs(r)), (s, f, g, r)
-    got = lat.get_state(0)
-    rng = np.random.default_rng(5)
-    idx = tuple(rng.integers(0, n, size=(3, 4096)))
-    assert _rel(got[idx], ostate[idx]) < 1e-3
+    e = max(abs(hist[s][0][f] - ohist[s][f]) / max(1.0, abs(ohist[s][f]))
+            for s in range(2) for f in ("energy", "energy_imag", "kinetic", "potential"))
+    check("complex.large_first_steps.energies", e, 4e-8)
+    check("complex.large_first_steps.state", _rel(lat.get_state(0), ostate), 2e-6)
     lat.close()
 
 

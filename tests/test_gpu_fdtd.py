@@ -3,13 +3,13 @@ with psi = 0 outside the box), one fused stencil + update + sums pass per state,
 through the C ABI, against the FP64 oracle.
 
 Tolerances: FP64 lattices 1e-12 (max-abs / max) for one kinetic application and
-1e-10 relative for energies along trajectories; FP32 lattices 1e-6 of the largest
-value for one application (a few FP32 roundings per site) and 1e-5 relative on
-energies."""
+1e-10 relative for energies along trajectories; FP32 lattices about four times the
+largest error measured on an MI355X (printed by each run, see measure.py)."""
 import numpy as np
 import pytest
 
 import synth
+from measure import check, max_rel_energy
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +37,10 @@ def test_fdtd_apply_kinetic(itse, orc, n, prec):
     lat.set_state(0, psi)
     got = lat.apply_kinetic(0).cpu().numpy().astype(np.float64)
     ref = orc.apply_kinetic(_olat(orc, lat), psi.astype(np.float64))
-    assert _rel(got, ref) < (1e-12 if prec == "fp64" else 1e-6)
+    if prec == "fp64":
+        assert _rel(got, ref) < 1e-12
+    else:
+        check(f"fdtd.apply_kinetic[{n}]", _rel(got, ref), 8e-7)
     lat.close()
 
 
@@ -63,16 +66,15 @@ def test_fdtd_multistate_steps(itse, orc, n, prec, center, parity, axes):
     hist = lat.history(steps)
     ostates, ohist = orc.step(_olat(orc, lat), [s.astype(np.float64) for s in states], v.astype(np.float64),
                               steps, parity=parity, axes=axes)
-    etol = 1e-10 if prec == "fp64" else 1e-5
-    for s in range(steps):
-        for i in range(3):
-            for f in ("energy", "norm2", "x", "r2"):
-                g, r = hist[s][i][f], ohist[s][i][f]
-                assert abs(g - r) <= etol * max(1.0, abs(r)), (s, i, f, g, r)
-            # no column pass: the parity weight is reported as not formed
-            assert hist[s][i]["parity_even"] == -1.0
-    for i in range(3):
-        assert _rel(lat.get_state(i), ostates[i]) < (1e-10 if prec == "fp64" else 1e-4)
+    e = max_rel_energy(hist, ohist, ("energy", "norm2", "x", "r2"), floor=1.0)
+    # no column pass: the parity weight is reported as not formed
+    assert all(hist[s][i]["parity_even"] == -1.0 for s in range(steps) for i in range(3))
+    st = max(_rel(lat.get_state(i), ostates[i]) for i in range(3))
+    if prec == "fp64":
+        assert e <= 1e-10 and st <= 1e-10, (e, st)
+    else:
+        check(f"fdtd.multistate[{n}].energies", e, 1.7e-7)
+        check(f"fdtd.multistate[{n}].states", st, 1.5e-6)
     lat.close()
 
 
@@ -91,10 +93,7 @@ def test_fdtd_large_first_steps(itse, orc):
     hist = lat.history(2)
     _, ohist = orc.step(_olat(orc, lat), [s.astype(np.float64) for s in states], v.astype(np.float64), 2,
                         parity=(1, -1, -1))
-    for s in range(2):
-        for i in range(3):
-            g, r = hist[s][i]["energy"], ohist[s][i]["energy"]
-            assert abs(g - r) <= 1e-5 * abs(r), (s, i, g, r)
+    check("fdtd.large_first_steps.energies", max_rel_energy(hist, ohist), 1.8e-7)
     lat.close()
 
 

@@ -4,14 +4,15 @@ Tolerances:
 * FP64 lattices: 1e-12 relative (max-abs / max) for single transforms and
   kinetic applications; 1e-10 relative for energies and states along whole
   trajectories.
-* FP32 lattices (FP32 storage and transforms, FP64 sums): one transform has a
-  relative error ~ eps32 * log2(N) (6e-8 * 8 at N = 256); the bound used is
-  2e-5 of max|K psi| element-wise and 1e-5 relative on energies of a step.
+* FP32 lattices (FP32 storage and transforms, FP64 sums): bounds at about four
+  times the largest error measured on an MI355X (the figures are printed by
+  each run, see measure.py).
 """
 import numpy as np
 import pytest
 
 import synth
+from measure import check, max_rel_energy
 
 pytestmark = pytest.mark.gpu
 
@@ -68,7 +69,7 @@ def test_apply_kinetic_fp32(itse, orc, n, kin, sub):
     lat.set_state(0, psi)
     got = lat.apply_kinetic(0).cpu().numpy().astype(np.float64)
     ref = orc.apply_kinetic(_olat(orc, lat), psi.astype(np.float64))
-    assert _rel(got, ref) < 2e-5
+    check(f"parity.apply_kinetic_fp32[{n},{kin}]", _rel(got, ref), 2e-6)
 
 
 def test_plain_config_trajectory(itse, orc):
@@ -152,10 +153,7 @@ def test_fp32_step_energies(itse, orc):
     hist = lat.history(20)
     _, ohist = orc.step(_olat(orc, lat), [s.astype(np.float64) for s in states],
                         v.astype(np.float64), 20, parity=(1, -1))
-    for s in range(20):
-        for i in range(2):
-            g, r = hist[s][i]["energy"], ohist[s][i]["energy"]
-            assert abs(g - r) <= 1e-5 * abs(r), (s, i, g, r)
+    check("parity.fp32_step_energies", max_rel_energy(hist, ohist), 1.2e-7)
     lat.close()
 
 

@@ -4,8 +4,8 @@ against the FP64 oracle.
 
 Tolerances: FP64 lattices 1e-12 (max-abs / max) for one transform or kinetic
 application and 1e-10 relative for energies along trajectories.  FP32 lattices:
-one transform rounds to ~eps32 * log2(N) relative (6e-8 * 8 at N = 256); the
-bound used is 2e-5 of the largest value, and 1e-5 relative on step energies.
+bounds at about four times the largest error measured on an MI355X (printed by
+each run, see measure.py).
 """
 import json
 
@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import synth
+from measure import check, max_rel_energy
 
 pytestmark = pytest.mark.gpu
 
@@ -23,7 +24,7 @@ CASES = [(48, "fp64", 0), (96, "fp64", 0), (128, "fp32", 0), (128, "fp32", 1), (
 
 
 def _tol(prec):
-    return 1e-12 if prec == "fp64" else 2e-5
+    return 1e-12 if prec == "fp64" else 2e-6
 
 
 def _rel(a, b):
@@ -64,7 +65,7 @@ def test_schedule_per_kind(itse, orc):
     lat.set_state(0, psi)
     got = lat.apply_kinetic(0).cpu().numpy().astype(np.float64)
     ref = orc.apply_kinetic(_olat(orc, lat), psi.astype(np.float64))
-    assert _rel(got, ref) < 2e-5
+    check("passes.schedule_per_kind", _rel(got, ref), 2e-6)
     lat.close()
 
 
@@ -78,7 +79,10 @@ def test_spectrum_schedules(itse, orc, n, prec, variant):
     spec = lat.spectrum(0).cpu().numpy().astype(np.float64)
     got = spec[..., 0] + 1j * spec[..., 1]
     ref = orc.fft3d(psi.astype(np.float64), -1)[:, :, : n // 2 + 1]
-    assert _rel(got, ref) < _tol(prec)
+    if prec == "fp32":
+        check(f"passes.spectrum[{n},{variant}]", _rel(got, ref), 7.5e-7)
+    else:
+        assert _rel(got, ref) < _tol(prec)
     lat.close()
 
 
@@ -91,7 +95,10 @@ def test_kinetic_schedules(itse, orc, n, prec, variant, kin):
     lat.set_state(0, psi)
     got = lat.apply_kinetic(0).cpu().numpy().astype(np.float64)
     ref = orc.apply_kinetic(_olat(orc, lat), psi.astype(np.float64))
-    assert _rel(got, ref) < _tol(prec)
+    if prec == "fp32":
+        check(f"passes.kinetic[{n},{variant},{kin}]", _rel(got, ref), _tol(prec))
+    else:
+        assert _rel(got, ref) < _tol(prec)
     lat.close()
 
 
@@ -114,15 +121,13 @@ def test_multistate_steps_large(itse, orc, n, prec, variant):
     hist = lat.history(steps)
     ostates, ohist = orc.step(_olat(orc, lat), [s.astype(np.float64) for s in states],
                               v.astype(np.float64), steps, parity=(1, -1, -1))
-    etol = 1e-10 if prec == "fp64" else 1e-5
-    for s in range(steps):
-        for i in range(3):
-            for f in ("energy", "norm2", "x", "r2", "parity_even"):
-                g, r = hist[s][i][f], ohist[s][i][f]
-                assert abs(g - r) <= etol * max(1.0, abs(r)), (s, i, f, g, r)
-    stol = 1e-10 if prec == "fp64" else 1e-4
-    for i in range(3):
-        assert _rel(lat.get_state(i), ostates[i]) < stol
+    e = max_rel_energy(hist, ohist, ("energy", "norm2", "x", "r2", "parity_even"), floor=1.0)
+    st = max(_rel(lat.get_state(i), ostates[i]) for i in range(3))
+    if prec == "fp64":
+        assert e <= 1e-10 and st <= 1e-10, (e, st)
+    else:
+        check(f"passes.multistate_large[{n}].energies", e, 2.2e-7)
+        check(f"passes.multistate_large[{n}].states", st, 1.7e-6)
     lat.close()
 
 
@@ -149,15 +154,13 @@ def test_projection_modes(itse, orc, n, prec, parity, axes, ortho):
     hist = lat.history(steps)
     ostates, ohist = orc.step(_olat(orc, lat), [s.astype(np.float64) for s in states],
                               v.astype(np.float64), steps, ortho_every=ortho, parity=parity, axes=axes)
-    etol = 1e-10 if prec == "fp64" else 1e-5
-    for s in range(steps):
-        for i in range(3):
-            for f in ("energy", "norm2", "z", "parity_even"):
-                g, r = hist[s][i][f], ohist[s][i][f]
-                assert abs(g - r) <= etol * max(1.0, abs(r)), (s, i, f, g, r)
-    stol = 1e-10 if prec == "fp64" else 1e-4
-    for i in range(3):
-        assert _rel(lat.get_state(i), ostates[i]) < stol
+    e = max_rel_energy(hist, ohist, ("energy", "norm2", "z", "parity_even"), floor=1.0)
+    st = max(_rel(lat.get_state(i), ostates[i]) for i in range(3))
+    if prec == "fp64":
+        assert e <= 1e-10 and st <= 1e-10, (e, st)
+    else:
+        check(f"passes.projection_modes[{n},{parity},{axes}].energies", e, 2.7e-7)
+        check(f"passes.projection_modes[{n},{parity},{axes}].states", st, 2.1e-6)
     lat.close()
 
 
@@ -186,42 +189,13 @@ def test_projection_origin_axes(itse, orc, n, prec, parity, axes):
     hist = lat.history(steps)
     ostates, ohist = orc.step(_olat(orc, lat), [s.astype(np.float64) for s in states],
                               v.astype(np.float64), steps, ortho_every=1, parity=parity, axes=axes)
-    etol = 1e-10 if prec == "fp64" else 1e-5
-    for s in range(steps):
-        for i in range(3):
-            for f in ("energy", "norm2", "parity_even"):
-                g, r = hist[s][i][f], ohist[s][i][f]
-                assert abs(g - r) <= etol * max(1.0, abs(r)), (s, i, f, g, r)
-    stol = 1e-10 if prec == "fp64" else 1e-4
-    for i in range(3):
-        assert _rel(lat.get_state(i), ostates[i]) < stol
-    lat.close()
-
-
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
-def test_precision_workload_first_steps(itse, orc, variant):
-    """The 256^3 FP32 workload the benchmark times, in every schedule the autotuner
-    may pick: the energies of the first steps match the FP64 oracle on the same
-    FP32 inputs."""
-    p = synth.config_precision(256)
-    v = p.potential_array(np.float64).astype(np.float32)
-    states = [s.astype(np.float32) for s in p.initial_states()]
-    itse.set_schedule(256, "fp32", variant)
-    lat = itse.Lattice(p.n, p.a, p.mass, p.dtau, kin=p.kin, subtract_rest_mass=True,
-                       precision="fp32", center=p.center, nstates=p.nstates)
-    lat.set_potential(v)
-    for i, s in enumerate(states):
-        lat.set_state(i, s)
-    lat.set_options(ortho_every=1, moments=False, parity=list(p.parity))
-    steps = 2
-    lat.step(steps)
-    hist = lat.history(steps)
-    _, ohist = orc.step(_olat(orc, lat), [s.astype(np.float64) for s in states],
-                        v.astype(np.float64), steps, parity=list(p.parity), record=True)
-    for s in range(steps):
-        for i in range(p.nstates):
-            g, r = hist[s][i]["energy"], ohist[s][i]["energy"]
-            assert abs(g - r) <= 1e-5 * abs(r), (s, i, g, r)
+    e = max_rel_energy(hist, ohist, ("energy", "norm2", "parity_even"), floor=1.0)
+    st = max(_rel(lat.get_state(i), ostates[i]) for i in range(3))
+    if prec == "fp64":
+        assert e <= 1e-10 and st <= 1e-10, (e, st)
+    else:
+        check(f"passes.projection_origin_axes[{n},{parity},{axes}].energies", e, 1.9e-7)
+        check(f"passes.projection_origin_axes[{n},{parity},{axes}].states", st, 1.5e-6)
     lat.close()
 
 
@@ -244,8 +218,6 @@ def test_bare_one_state_steps(itse, orc, variant):
     lat.step(steps)
     hist = lat.history(steps)
     ostates, ohist = orc.step(_olat(orc, lat), [psi.astype(np.float64)], v.astype(np.float64), steps)
-    for s in range(steps):
-        g, r = hist[s][0]["energy"], ohist[s][0]["energy"]
-        assert abs(g - r) <= 1e-5 * abs(r), (s, g, r)
-    assert _rel(lat.get_state(0), ostates[0]) < 1e-4
+    check(f"passes.bare_one_state[{variant}].energies", max_rel_energy(hist, ohist, ("energy", "norm2")), 4.8e-8)
+    check(f"passes.bare_one_state[{variant}].state", _rel(lat.get_state(0), ostates[0]), 1.9e-6)
     lat.close()

@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 import synth
+from measure import check
 
 pytestmark = pytest.mark.gpu
 
@@ -61,10 +62,10 @@ def oracle_e0(orc):
 
 
 # FP64: stop at 1e-12 relative change, agree with the oracle to 1e-6 (the map's
-# second-order bias, about 3e-7).  FP32 states and transforms with FP64 sums: the
-# energy's FP32 floor is near 1e-8 relative, so stop at 1e-8 and agree to 1e-5,
-# the FP32 energy tolerance of the parity tests.
-@pytest.mark.parametrize("prec,tol,rel", [("fp64", 1e-12, 1e-6), ("fp32", 1e-8, 1e-5)])
+# second-order bias, about 3e-7).  FP32 states and transforms with FP64 sums: stop
+# at 1e-8 relative change and agree to about four times the difference measured
+# on an MI355X (the same map bias plus FP32 rounding).
+@pytest.mark.parametrize("prec,tol,rel", [("fp64", 1e-12, 1e-6), ("fp32", 1e-8, 1.1e-6)])
 def test_relativistic_oscillator_ground_state(itse, oracle_e0, prec, tol, rel):
     g, A, M, n, v, guess = _problem()
     dt = np.float64 if prec == "fp64" else np.float32
@@ -80,5 +81,7 @@ def test_relativistic_oscillator_ground_state(itse, oracle_e0, prec, tol, rel):
     print(f"\n{prec} E0 - M: GPU {e_gpu:.8f}, oracle eigenvalue {oracle_e0:.8f}, paper (analytic) {ref}",
           flush=True)
     assert abs(e_gpu - ref) <= g["E0_relative_agreement"] * ref, (e_gpu, ref)
+    if prec == "fp32":
+        check("physics.relativistic_oscillator_fp32", abs(e_gpu - oracle_e0) / abs(oracle_e0), rel)
     assert abs(e_gpu - oracle_e0) <= rel * abs(oracle_e0), (e_gpu, oracle_e0)
     lat.close()

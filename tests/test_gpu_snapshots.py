@@ -6,13 +6,15 @@ energies are compared with the oracle doing the same on the same inputs.
 
 Tolerances: FP64 lattices 1e-10 relative on energies and 1e-9 max-abs on the
 estimates (Gram-Schmidt of nearly parallel snapshots amplifies rounding by the
-condition number of the snapshot set, about 1e2 here); FP32 lattices 1e-5
-relative on the ground-state energy and 1e-3 on the excited estimates (FP32
-rounding of the evolution, amplified the same way)."""
+condition number of the snapshot set, about 1e2 here); FP32 lattices about four
+times the largest error measured on an MI355X, for the ground-state energy and
+for the excited estimates apart (FP32 rounding of the evolution, amplified the
+same way), printed by each run (see measure.py)."""
 import numpy as np
 import pytest
 
 import synth
+from measure import check
 
 pytestmark = pytest.mark.gpu
 
@@ -59,16 +61,20 @@ def test_snapshot_extraction_matches_oracle(itse, orc, n, prec, kin, center, pot
     assert np.array_equal(before, lat.get_state(0))        # the lattice is not changed
     oest, oobs = orc.snapshot_extract(L, state[0], snaps[::-1], v)
     assert len(obs) == 3
-    for k in range(3):
-        tol = 1e-10 if prec == "fp64" else (1e-5 if k == 0 else 1e-3)
-        g, r = obs[k]["energy"], oobs[k]["energy"]
-        assert abs(g - r) <= tol * max(1.0, abs(r)), (k, g, r)
-        assert abs(obs[k]["norm2"] - 1.0) < (1e-12 if prec == "fp64" else 1e-5)
-        if prec == "fp64":
-            assert np.abs(est[k] - oest[k]).max() < 1e-9, k
+    errs = [abs(obs[k]["energy"] - oobs[k]["energy"]) / max(1.0, abs(oobs[k]["energy"])) for k in range(3)]
+    nerr = max(abs(obs[k]["norm2"] - 1.0) for k in range(3))
     # estimates are orthonormal
     gram = np.einsum("aijk,bijk->ab", est, est)
-    assert np.abs(gram - np.eye(3)).max() < (1e-12 if prec == "fp64" else 1e-5)
+    gerr = np.abs(gram - np.eye(3)).max()
+    if prec == "fp64":
+        assert max(errs) <= 1e-10 and nerr < 1e-12 and gerr < 1e-12, (errs, nerr, gerr)
+        for k in range(3):
+            assert np.abs(est[k] - oest[k]).max() < 1e-9, k
+    else:
+        check(f"snapshots.extract[{n}].ground_energy", errs[0], 5.8e-7)
+        check(f"snapshots.extract[{n}].excited_energies", max(errs[1:]), 2.9e-7)
+        check(f"snapshots.extract[{n}].norms", nerr, 3.3e-9)
+        check(f"snapshots.extract[{n}].gram", gerr, 3.4e-9)
     lat.close()
 
 
