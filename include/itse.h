@@ -244,6 +244,18 @@ typedef struct {
  * Synchronises.  Errors: ITSE_EINVAL, ITSE_ENONFINITE if the box holds no weight. */
 itse_status itse_analyse(itse_lattice *lat, int i, double min_sep_edge, itse_analysis *out);
 
+/* itse_analyse for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid allocation): the same
+ * kernels and results, with the partial sums in a fixed workspace the library
+ * holds on each GPU it runs on (112 KiB per GPU, held until the process ends; it
+ * covers every supported n, and a larger need is refused with ITSE_EINVAL).  No
+ * device memory is allocated or freed by the call.  The workspace is shared by
+ * all calls on one GPU: calls that overlap on the same GPU (from several
+ * threads or on several streams) race, and the caller must order them.
+ * Synchronises the lattice's stream.  Errors as for itse_analyse, and
+ * ITSE_EDEVICE if the workspace's address cannot be obtained. */
+itse_status itse_analyse_noalloc(itse_lattice *lat, int i, double min_sep_edge, itse_analysis *out);
+
 /* Radial momentum-space wave-function of state i: Psi(p) = FFT[psi] scaled so that
  * (2 pi / (N A))^3 sum_p |Psi(p)|^2 = 1, p on the eigenmode set; momenta grouped in
  * bins of width 2 pi / (N A) (bin b: |p| in [(b - 1/2), (b + 1/2)) 2 pi / (N A)),

@@ -119,6 +119,7 @@ def load():
         "itse_polish": ([vp, ip, P(Obs)], ip),
         "itse_sync": ([vp], ip),
         "itse_analyse": ([vp, ip, ctypes.c_double, P(Analysis)], ip),
+        "itse_analyse_noalloc": ([vp, ip, ctypes.c_double, P(Analysis)], ip),
         "itse_momentum_radial": ([vp, ip, ip, P(dp), P(dp), P(dp), P(dp)], ip),
         "itse_snapshot_push": ([vp], ip),
         "itse_snapshot_count": ([vp, P(ip)], ip),

@@ -49,6 +49,7 @@ hipError_t launch_check_potential(const LatDev *lat, int prec, hipStream_t s);
 
 struct itse_lattice {
     itse_desc d{};
+    int device = 0;                 // HIP device current at create
     hipStream_t stream = nullptr;
     itse_alloc_fn alloc = nullptr;
     itse_free_fn freefn = nullptr;

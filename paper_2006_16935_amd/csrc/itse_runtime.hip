@@ -646,6 +646,7 @@ extern "C" itse_status itse_create(const itse_desc *d, void *hip_stream, itse_al
     L->d = *d;
     if (d->complex_psi) L->d.nstates = 2;  // Re psi and Im psi
     L->stream = (hipStream_t)hip_stream;
+    HIPCHK(hipGetDevice(&L->device));
     L->alloc = alloc;
     L->freefn = free_fn;
     L->alloc_user = alloc_user;
@@ -1261,15 +1262,25 @@ static double *ana_scratch(itse_lattice *L, size_t doubles) {
     return L->ana;
 }
 
-extern "C" itse_status itse_analyse(itse_lattice *L, int i, double min_sep_edge, itse_analysis *out) {
-    if (L && L->host.cplx) return fail(ITSE_ESTATE, "%s: real states only", "itse_analyse");
+// The analysis kernels (partial sums per workgroup, then their fixed-order sum)
+// into the workspace buf of at least analyse_doubles(n) doubles; results to out.
+static size_t analyse_doubles(const itse_lattice *L) {
+    const int n = L->d.n;
+    return (L->d.precision == ITSE_FP32 ? Launch<float>::analyse_parts(n) : Launch<double>::analyse_parts(n)) + NAQ;
+}
+
+static itse_status analyse_checks(itse_lattice *L, int i, double min_sep_edge, itse_analysis *out,
+                                  const char *who) {
+    if (L && L->host.cplx) return fail(ITSE_ESTATE, "%s: real states only", who);
     if (!L || !out) return fail(ITSE_EINVAL, "null argument");
     if (i < 0 || i >= L->d.nstates) return fail(ITSE_EINVAL, "state index %d", i);
     if (!(min_sep_edge >= 0.0 && min_sep_edge < 1.0)) return fail(ITSE_EINVAL, "min_sep_edge = %g", min_sep_edge);
+    return ITSE_OK;
+}
+
+static itse_status analyse_into(itse_lattice *L, int i, double min_sep_edge, double *buf, itse_analysis *out) {
     const int n = L->d.n;
-    const size_t np = L->d.precision == ITSE_FP32 ? Launch<float>::analyse_parts(n) : Launch<double>::analyse_parts(n);
-    double *buf = ana_scratch(L, np + NAQ);
-    if (!buf) return fail(ITSE_ENOMEM, "analysis sums");
+    const size_t np = analyse_doubles(L) - NAQ;
     const double half = (1.0 - min_sep_edge) * n * L->d.a / 2.0;
     hipError_t e = L->d.precision == ITSE_FP32
                        ? Launch<float>::analyse(n, L->jobs_dev + i, half, buf, buf + np, L->stream)
@@ -1287,6 +1298,65 @@ extern "C" itse_status itse_analyse(itse_lattice *L, int i, double min_sep_edge,
     out->w_minus_axis[1] = q[NA_PE2] / q[NA_NORM];
     out->w_minus_axis[2] = q[NA_PE3] / q[NA_NORM];
     return ITSE_OK;
+}
+
+extern "C" itse_status itse_analyse(itse_lattice *L, int i, double min_sep_edge, itse_analysis *out) {
+    itse_status st = analyse_checks(L, i, min_sep_edge, out, "itse_analyse");
+    if (st) return st;
+    double *buf = ana_scratch(L, analyse_doubles(L));
+    if (!buf) return fail(ITSE_ENOMEM, "analysis sums");
+    return analyse_into(L, i, min_sep_edge, buf, out);
+}
+
+// ------------------------------------------------------------------------------------
+// The analysis without allocation: its workspace is a file-scope device array,
+// one copy per GPU, sized for the largest supported lattice (n = 256: 256 x 8
+// workgroups x 7 partial sums + 7 totals, 112 KiB).  Every kernel writes each
+// slot it later reads (the partial sums, then the totals), so nothing needs
+// clearing between calls.  Calls on one GPU share the array: calls that overlap
+// on one GPU (different streams, or threads) race and must be ordered by the
+// caller.
+// ------------------------------------------------------------------------------------
+constexpr size_t ANA_SCRATCH_DOUBLES = (size_t)256 * ANA_CHUNKS * NAQ + NAQ;
+static __device__ __align__(256) double scratch[ANA_SCRATCH_DOUBLES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, double *> g_scratch_ptr;  // device -> address of `scratch` on it
+
+// Address of the workspace on the lattice's device, looked up once per device with
+// that device current (the name of the array is a host-side stand-in, not a device
+// address).
+static itse_status scratch_on(int device, double **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return ITSE_OK;
+    }
+    int cur = 0;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != device) HIPCHK(hipSetDevice(device));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) HIPCHK(hipSetDevice(cur));
+    if (e != hipSuccess || !p) return fail(ITSE_EDEVICE, "workspace address on device %d: %s", device,
+                                           hipGetErrorString(e));
+    g_scratch_ptr[device] = (double *)p;
+    *out = (double *)p;
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_analyse_noalloc(itse_lattice *L, int i, double min_sep_edge, itse_analysis *out) {
+    itse_status st = analyse_checks(L, i, min_sep_edge, out, "itse_analyse_noalloc");
+    if (st) return st;
+    const size_t need = analyse_doubles(L);
+    if (need > ANA_SCRATCH_DOUBLES)
+        return fail(ITSE_EINVAL, "itse_analyse_noalloc: n = %d needs %zu workspace doubles, the limit is %zu",
+                    L->d.n, need, ANA_SCRATCH_DOUBLES);
+    double *buf = nullptr;
+    st = scratch_on(L->device, &buf);
+    if (st) return st;
+    return analyse_into(L, i, min_sep_edge, buf, out);
 }
 
 extern "C" itse_status itse_momentum_radial(itse_lattice *L, int i, int nbins, double *count, double *p, double *psi,

@@ -281,6 +281,13 @@ class Lattice:
         check(self._L.itse_analyse(self.h, int(i), float(min_sep_edge), ctypes.byref(out)))
         return out.as_dict()
 
+    def analyse_noalloc(self, i: int, min_sep_edge: float = 0.3) -> dict:
+        """analyse() through itse_analyse_noalloc: the same results with no device
+        allocation (the library's fixed per-GPU workspace)."""
+        out = _lib.Analysis()
+        check(self._L.itse_analyse_noalloc(self.h, int(i), float(min_sep_edge), ctypes.byref(out)))
+        return out.as_dict()
+
     def momentum_radial(self, i: int, nbins: int) -> dict:
         """Radial momentum-space wave-function of state i in bins of 2 pi / (N A):
         arrays count, p, psi (mean |Psi(p)|) and y = sqrt(4 pi) p psi."""
