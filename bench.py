@@ -216,6 +216,9 @@ def batch_leg(torch, itse, steps: int, warmup: int, count: int = 64):
     each, FP32 with FP64 sums, stepped together; aggregate site-steps/s."""
     import synth
     probs = synth.batch_problems(count=count, seed=0, nstates=2)
+    # schedules per size picked by the library's autotuner before the lattices are
+    # created (a lattice takes the schedule current at its creation)
+    tuned = {n: json.loads(itse.autotune(n, "fp32")) for n in sorted({p.n for p in probs})}
     lats = []
     for p in probs:
         lat = itse.Lattice(p.n, p.a, p.mass, p.dtau, kin=p.kin, subtract_rest_mass=p.subtract_rest_mass,
@@ -244,7 +247,8 @@ def batch_leg(torch, itse, steps: int, warmup: int, count: int = 64):
     for lat in lats:
         lat.close()
     return {"site_steps_per_s": sites * steps / secs, "ms_per_step": secs * 1000.0 / steps,
-            "lattices": count, "sizes": sizes, "steps": steps, "site_steps_per_step": sites}
+            "lattices": count, "sizes": sizes, "steps": steps, "site_steps_per_step": sites,
+            "schedules": {n: t["best"] for n, t in tuned.items()}}
 
 
 def serving_run(torch, itse, count: int, qps: float, budget: int, seed: int = 1):

@@ -13,6 +13,22 @@ struct NVariants {
     static constexpr int value = 1;
 };
 template <>
+struct NVariants<float, 32> {
+    static constexpr int value = 2;
+};
+template <>
+struct NVariants<float, 48> {
+    static constexpr int value = 3;
+};
+template <>
+struct NVariants<float, 64> {
+    static constexpr int value = 3;
+};
+template <>
+struct NVariants<float, 96> {
+    static constexpr int value = 3;
+};
+template <>
 struct NVariants<float, 128> {
     static constexpr int value = 2;
 };

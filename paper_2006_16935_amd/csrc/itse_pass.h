@@ -107,6 +107,16 @@ ITSE_PLAN(float, 32, 0, 1, 4, 17, 1)
 ITSE_PLAN(float, 48, 0, 1, 4, 16, 1)
 ITSE_PLAN(float, 64, 0, 1, 4, 16, 1)
 ITSE_PLAN(float, 96, 0, 1, 4, 16, 2)
+// the batch sizes: column workgroups of four waves (one kz chunk of W = 20 at
+// N = 32: the whole half row), and the y axis split in two (twice the plane
+// workgroups, for batches of few lattices)
+ITSE_PLAN(float, 32, 1, 1, 4, 20, 4)
+ITSE_PLAN(float, 48, 1, 1, 4, 16, 4)
+ITSE_PLAN(float, 48, 2, 2, 4, 16, 4)
+ITSE_PLAN(float, 64, 1, 1, 4, 16, 4)
+ITSE_PLAN(float, 64, 2, 2, 4, 16, 4)
+ITSE_PLAN(float, 96, 1, 1, 4, 16, 4)
+ITSE_PLAN(float, 96, 2, 2, 4, 16, 4)
 ITSE_PLAN(float, 128, 0, 1, 8, 16, 2)
 ITSE_PLAN(float, 128, 1, 2, 4, 16, 4)
 ITSE_PLAN(float, 192, 0, 2, 8, 16, 8)

@@ -63,6 +63,40 @@ def test_batched_mix_matches_oracle_and_alone(itse, orc):
         lat.close()
 
 
+@pytest.mark.parametrize("variant", [1, 2])
+def test_batched_mix_under_other_schedules(itse, orc, variant):
+    """The batched-form mix under the other schedules of the batch sizes (column
+    workgroups of four waves; the y axis split in two where the size has it): the
+    batch equals each lattice stepped alone bitwise, and the energies follow the
+    oracle."""
+    probs = synth.batch_problems(count=8, seed=5, nstates=2)
+    for n in (32, 48, 64, 96):
+        itse.set_schedule(n, "fp32", min(variant, itse.schedule_variants(n, "fp32") - 1))
+    try:
+        steps = 12
+        alone = [_make(itse, p) for p in probs]
+        mixed = [_make(itse, p) for p in probs]
+    finally:
+        for n in (32, 48, 64, 96):
+            itse.set_schedule(n, "fp32", 0)
+    for lat in alone:
+        lat.step(steps)
+    batch = itse.Batch(mixed)
+    batch.step(steps)
+    for p, la, lb in zip(probs, alone, mixed):
+        for i in range(p.nstates):
+            assert np.array_equal(la.get_state(i, np.float32), lb.get_state(i, np.float32))
+    for j in (0, 3, 7):
+        p = probs[j]
+        v = p.potential_array(np.float64).astype(np.float32).astype(np.float64)
+        states = [s.astype(np.float32).astype(np.float64) for s in p.initial_states()]
+        _, oh = orc.step(_olat(orc, p), states, v, steps)
+        check(f"batch.schedule{variant}_energies[{j}]", max_rel_energy(mixed[j].history(steps), oh), 2.5e-7)
+    batch.close()
+    for lat in alone + mixed:
+        lat.close()
+
+
 def _request(itse, server, p, tol=1e-7, keep=False, precision="fp32", max_steps=20000):
     dt = np.float32 if precision == "fp32" else np.float64
     return server.submit(p.n, p.a, p.mass, p.dtau, p.potential_array(np.float64).astype(dt),
