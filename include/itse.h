@@ -318,6 +318,18 @@ itse_status itse_batch_create(int count, itse_lattice *const *lats, void *hip_st
                               itse_batch **out);
 itse_status itse_batch_step(itse_batch *b, int nsteps);
 itse_status itse_batch_destroy(itse_batch *b);
+/* Persistent stepping (on = 1): each itse_batch_step is then one cooperative launch
+ * of a kernel whose resident workgroups run the passes of every lattice of the
+ * batch for all the steps, the passes separated by grid-wide barriers (the tiles
+ * are those of the passes' own kernels, so results stay bitwise those of each
+ * lattice stepped alone).  Takes FP32 transform lattices of real states with N in
+ * {32, 48, 64, 96} created under a schedule variant whose plane and column
+ * workgroups have 256 threads (1, or 2 where N has it), at most two states, in at
+ * most eight groups of equal (N, schedule); otherwise ITSE_EINVAL.  Steps whose options need position moments or
+ * projections of states along different axes take the graph path.  on = 0
+ * returns to graph replay (the default, and the faster path on MI355X: each
+ * grid-wide barrier there costs tens of microseconds, several per step). */
+itse_status itse_batch_set_persistent(itse_batch *b, int on);
 
 /* ---- schedules ------------------------------------------------------------------ */
 /* Schedules are kept per (n, precision) and per kind of lattice: one state, or

@@ -128,6 +128,7 @@ def load():
         "itse_profile_step": ([vp, ip, P(dp), P(ip), ctypes.c_char_p, ctypes.c_size_t], ip),
         "itse_batch_create": ([ip, P(vp), vp, P(vp)], ip),
         "itse_batch_step": ([vp, ip], ip),
+        "itse_batch_set_persistent": ([vp, ip], ip),
         "itse_batch_destroy": ([vp], ip),
         "itse_autotune": ([ip, ip, vp, ctypes.c_char_p, ctypes.c_size_t], ip),
         "itse_schedule_get": ([ip, ip, ctypes.c_char_p, ctypes.c_size_t], ip),

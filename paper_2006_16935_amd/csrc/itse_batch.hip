@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "itse_internal.h"
+#include "itse_persist.h"
 #include "itse_runtime.h"
 
 using namespace itse;
@@ -40,6 +41,10 @@ struct itse_batch {
     std::vector<void *> dev_arrays;
     hipGraphExec_t graph1 = nullptr, graphN = nullptr;
     std::vector<hipEvent_t> evs;
+    bool persistent = false;     // step through the persistent kernel
+    int persist_blocks = 0;      // its cooperative grid
+    PersistPlan pplan{};         // host copy of the plan
+    PersistPlan *pplan_dev = nullptr;
 };
 
 // ------------------------------------------------------------------------------------
@@ -198,6 +203,54 @@ extern "C" itse_status itse_batch_create(int count, itse_lattice *const *lats, v
     return ITSE_OK;
 }
 
+extern "C" itse_status itse_batch_set_persistent(itse_batch *B, int on) {
+    if (!B) return fail(ITSE_EINVAL, "null batch");
+    if (!on) {
+        B->persistent = false;
+        return ITSE_OK;
+    }
+    if (B->groups.size() > (size_t)PERSIST_GROUPS)
+        return fail(ITSE_EINVAL, "persistent batches hold at most %d groups of equal shape", PERSIST_GROUPS);
+    PersistPlan pl{};
+    pl.ngroups = (int)B->groups.size();
+    for (size_t gi = 0; gi < B->groups.size(); ++gi) {
+        const Group &g = B->groups[gi];
+        if (g.fdtd || g.cplx || g.kmax > 2 || !persist_shape_ok(g.n, g.prec, g.variant))
+            return fail(ITSE_EINVAL,
+                        "the persistent kernel takes FP32 transform lattices of real states, N in {32, 48, 64, "
+                        "96} under schedule variants with 256-thread plane and column workgroups (1, or 2 "
+                        "where N has it), at most two states (group n = %d, precision %d, variant %d, "
+                        "%d states)",
+                        g.n, g.prec, g.variant, g.kmax);
+        PersistGroup &q = pl.g[gi];
+        q.n = g.n;
+        q.variant = g.variant;
+        q.kmax = g.kmax;
+        q.gram = 0;
+        q.njobs = g.njobs;
+        q.nlats = g.nlats;
+        q.nb_plane = persist_nb_plane(g.n, g.variant);
+        q.nb_cols = persist_nb_cols(g.n, g.variant);
+        q.nb_gram = pg_blocks(g.n);
+        q.nq_fin = g.kmax * NQR + g.kmax * (g.kmax + 1) / 2;  // rows, Gram (no moments)
+        q.jobs = g.jobs;
+        q.lats = g.lats;
+    }
+    int blocks = 0;
+    hipError_t e = persist_grid(&blocks);
+    if (e != hipSuccess) return fail(ITSE_EDEVICE, "persistent grid: %s", hipGetErrorString(e));
+    if (!B->pplan_dev) {
+        void *p = nullptr;
+        if (hipMalloc(&p, sizeof(PersistPlan)) != hipSuccess) return fail(ITSE_ENOMEM, "persistent plan");
+        B->pplan_dev = (PersistPlan *)p;
+        B->dev_arrays.push_back(p);
+    }
+    B->pplan = pl;
+    B->persist_blocks = blocks;
+    B->persistent = true;
+    return ITSE_OK;
+}
+
 extern "C" itse_status itse_batch_step(itse_batch *B, int nsteps) {
     if (!B) return fail(ITSE_EINVAL, "null batch");
     if (nsteps < 0) return fail(ITSE_EINVAL, "nsteps < 0");
@@ -219,6 +272,27 @@ extern "C" itse_status itse_batch_step(itse_batch *B, int nsteps) {
         for (auto *L : B->members[gi]) needs |= step_needs(L->host, L->d.nstates);
         if (needs != B->groups[gi].needs) changed = true;
         B->groups[gi].needs = needs;
+    }
+    // the persistent kernel, when the steps need no per-state projection pass and no
+    // position moments (else the graph path)
+    bool persist = B->persistent;
+    for (size_t gi = 0; gi < B->groups.size() && persist; ++gi) {
+        if (B->groups[gi].needs & (NEED_PROJECT | NEED_MOMENTS)) persist = false;
+        B->pplan.g[gi].gram = (B->groups[gi].needs & NEED_GRAM) ? 1 : 0;
+    }
+    if (persist) {
+        HIPCHK(hipMemcpyAsync(B->pplan_dev, &B->pplan, sizeof(PersistPlan), hipMemcpyHostToDevice, B->stream));
+        hipError_t e = persist_launch(B->pplan_dev, nsteps, B->persist_blocks, B->stream);
+        if (e != hipSuccess) return fail(ITSE_EDEVICE, "persistent batch launch: %s", hipGetErrorString(e));
+        hipEvent_t done;
+        HIPCHK(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(done, B->stream));
+        for (auto *L : B->lats) {
+            if (L->stream != B->stream) HIPCHK(hipStreamWaitEvent(L->stream, done, 0));
+            L->steps_host += nsteps;
+        }
+        HIPCHK(hipEventDestroy(done));
+        return ITSE_OK;
     }
     if (changed && (B->graph1 || B->graphN)) {
         HIPCHK(hipStreamSynchronize(B->stream));

@@ -275,22 +275,33 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// The thread's index within its workgroup, hidden from loop-invariant code motion:
+// a tile run inside a loop over tiles (the persistent batch kernel) then forms its
+// per-thread addresses inside each tile, instead of hoisting them all before the
+// loop where they would stay live across every tile's transforms.
+__device__ __forceinline__ int tile_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    __builtin_assume(t >= 0 && t < 1024);
+    return t;
+}
+
 // Fixed-order workgroup sums of Q doubles; thread 0 writes dst[0..Q).
 template <int Q, int NTH>
 __device__ __forceinline__ void block_sums(double (&acc)[Q], double *dst, double *lds) {
     constexpr int NWV = NTH / 64;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tid = tile_tid(), lane = tid & 63, wv = tid >> 6;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const double s = wave_sum(acc[q]);
         if (lane == 0) lds[q * NWV + wv] = s;
     }
     __syncthreads();
-    if (threadIdx.x < Q) {
+    if (tid < Q) {
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < NWV; ++w) s += lds[threadIdx.x * NWV + w];
-        dst[threadIdx.x] = s;
+        for (int w = 0; w < NWV; ++w) s += lds[tid * NWV + w];
+        dst[tid] = s;
     }
 }
 
@@ -531,18 +542,17 @@ __device__ __forceinline__ void block_store_rows(const C2<R> *src, C2<R> *dst_, 
 // ---------------------------------------------------------------------------
 // P1: forward plane pass.  Sub-plane x * S + r and job from plane_block.
 // ---------------------------------------------------------------------------
+// The passes are written as tile functions (one workgroup's work: the tile's
+// indices and its LDS arrays are arguments), called by their own kernels and by
+// the persistent batch kernel.
 template <typename R, int N, int V, int KM>
-__global__ void __launch_bounds__((Geo<R, N, V>::NTP)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPE)))
-k_plane_fwd(const JobRef *__restrict__ jobs) {
+__device__ __forceinline__ void plane_fwd_tile(const JobRef *__restrict__ jobs, int spb, int jb, C2<R> *buf,
+                                               C2<R> *tw) {
     using G = Geo<R, N, V>;
     constexpr int S = G::S, M = G::M, H = G::H, HP = G::HP, LSZ = G::LSZ, PPW = G::PPW, CPW = G::CPW;
-    __shared__ __attribute__((aligned(16))) C2<R> buf[G::PLANE_ELEMS];
-    __shared__ C2<R> tw[N];
-    int jb;
-    const int spb = plane_block<G::NB_PLANE>(jb);
     const JobRef job = jobs[jb];
     const LatDev &L = *job.lat;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = tile_tid(), lane = tid & 63, wv = tid >> 6;
     const int x = spb / S, r = spb % S;
     const C2<R> *twg = (const C2<R> *)L.tw;
     for (int e = tid; e < N; e += G::NTP) tw[e] = twg[e];
@@ -617,6 +627,17 @@ k_plane_fwd(const JobRef *__restrict__ jobs) {
     block_store_rows<R, M * H, H, G::HS, HP, G::NTP>(buf, spec + ((size_t)r * N + x) * M * G::HS, tid);
 }
 
+template <typename R, int N, int V, int KM>
+__global__ void __launch_bounds__((Geo<R, N, V>::NTP)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPE)))
+k_plane_fwd(const JobRef *__restrict__ jobs) {
+    using G = Geo<R, N, V>;
+    __shared__ __attribute__((aligned(16))) C2<R> buf[G::PLANE_ELEMS];
+    __shared__ C2<R> tw[N];
+    int jb;
+    const int spb = plane_block<G::NB_PLANE>(jb);
+    plane_fwd_tile<R, N, V, KM>(jobs, spb, jb, buf, tw);
+}
+
 // ---------------------------------------------------------------------------
 // P2: column pass.  grid.x = ky' * NCH + chunk, grid.y = job.
 // mode COL_KIN: forward x transform, kinetic multiply (+ parity-weight sums
@@ -625,21 +646,15 @@ k_plane_fwd(const JobRef *__restrict__ jobs) {
 // [kx][ky][kz] at `out` (for the spectrum query).
 // ---------------------------------------------------------------------------
 template <typename R, int N, int V>
-__global__ void __launch_bounds__((Geo<R, N, V>::NTC)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPEC)))
-k_columns(const JobRef *__restrict__ jobs, int mode,
-                                                              int moments, C2<R> *__restrict__ out) {
+__device__ __forceinline__ void columns_tile(const JobRef *__restrict__ jobs, int blk, int jy, int mode, int moments,
+                                             C2<R> *__restrict__ out, C2<R> *buf, C2<R> *tw, double *ktab,
+                                             double *red) {
     using G = Geo<R, N, V>;
     constexpr int S = G::S, M = G::M, H = G::H, W = G::W, CS = G::CS, LPW = G::LPWC, NTC = G::NTC;
-    __shared__ __attribute__((aligned(16))) C2<R> buf[N * CS];
-    __shared__ C2<R> tw[N];
-    __shared__ double ktab[N];
-    __shared__ double red[NQC * (NTC / 64)];
-    const JobRef job = jobs[blockIdx.y];
+    const JobRef job = jobs[jy];
     const LatDev &L = *job.lat;
     const int i = job.state;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    // consecutive chunks of one ky' row share cache lines: keep them on one XCD
-    const int blk = xcd_local_index(blockIdx.x, gridDim.x);
+    const int tid = tile_tid(), lane = tid & 63, wv = tid >> 6;
     const int kyp = blk / G::NCH, kz0 = (blk % G::NCH) * W;
     const C2<R> *twg = (const C2<R> *)L.tw;
     for (int e = tid; e < N; e += NTC) {
@@ -881,6 +896,19 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
     }
 }
 
+template <typename R, int N, int V>
+__global__ void __launch_bounds__((Geo<R, N, V>::NTC)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPEC)))
+k_columns(const JobRef *__restrict__ jobs, int mode, int moments, C2<R> *__restrict__ out) {
+    using G = Geo<R, N, V>;
+    __shared__ __attribute__((aligned(16))) C2<R> buf[N * G::CS];
+    __shared__ C2<R> tw[N];
+    __shared__ double ktab[N];
+    __shared__ double red[NQC * (G::NTC / 64)];
+    // consecutive chunks of one ky' row share cache lines: keep them on one XCD
+    columns_tile<R, N, V>(jobs, xcd_local_index(blockIdx.x, gridDim.x), blockIdx.y, mode, moments, out, buf, tw,
+                          ktab, red);
+}
+
 // ---------------------------------------------------------------------------
 // P3: inverse plane pass + update.  Sub-plane x * S + r and job from plane_block.
 // mode INV_UPDATE: u_i <- ((1 - h V) psi - dtau K psi) / (1 + h V)   (= A psi - B dtau K psi)
@@ -895,20 +923,15 @@ k_columns(const JobRef *__restrict__ jobs, int mode,
 // and writes both parts' new arrays; besides its own row sums it forms
 // sum Vi |psi|^2 and sum |psi'|^2 (the complex-update sums).
 template <typename R, int N, int V, bool MOM, int KM, bool CPX = false>
-__global__ void __launch_bounds__((Geo<R, N, V>::NTP)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPE)))
-k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
+__device__ __forceinline__ void plane_inv_tile(const JobRef *__restrict__ jobs, int spb, int jb, int mode, C2<R> *buf,
+                                               C2<R> *tw, double *red) {
     using G = Geo<R, N, V>;
     constexpr int S = G::S, M = G::M, H = G::H, HP = G::HP, LSZ = G::LSZ, PPW = G::PPW, CPW = G::CPW;
     constexpr int NTP = G::NTP;
-    __shared__ __attribute__((aligned(16))) C2<R> buf[G::PLANE_ELEMS];
-    __shared__ C2<R> tw[N];
-    __shared__ double red[NQR * (NTP / 64)];
-    int jb;
-    const int spb = plane_block<G::NB_PLANE>(jb);
     const JobRef job = jobs[jb];
     const LatDev &L = *job.lat;
     const int i = job.state;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int tid = tile_tid(), lane = tid & 63, wv = tid >> 6;
     const int x = spb / S, r = spb % S;
     const C2<R> *twg = (const C2<R> *)L.tw;
     for (int e = tid; e < N; e += NTP) tw[e] = twg[e];
@@ -1090,6 +1113,18 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
         __syncthreads();
         block_sums<NQX, NTP>(xacc, L.part_cplx + (size_t)spb * NQX, red);
     }
+}
+
+template <typename R, int N, int V, bool MOM, int KM, bool CPX = false>
+__global__ void __launch_bounds__((Geo<R, N, V>::NTP)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPE)))
+k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
+    using G = Geo<R, N, V>;
+    __shared__ __attribute__((aligned(16))) C2<R> buf[G::PLANE_ELEMS];
+    __shared__ C2<R> tw[N];
+    __shared__ double red[NQR * (G::NTP / 64)];
+    int jb;
+    const int spb = plane_block<G::NB_PLANE>(jb);
+    plane_inv_tile<R, N, V, MOM, KM, CPX>(jobs, spb, jb, mode, buf, tw, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1444,7 +1479,8 @@ __global__ void __launch_bounds__(NT) k_project_gram(const JobRef *__restrict__ 
 // (x = xm, y = ym) is written and summed on its A side only.
 // ---------------------------------------------------------------------------
 template <typename R, int KM, int N>
-__global__ void __launch_bounds__(NT) k_project_gram_vec(const JobRef *__restrict__ lats, int force, int which) {
+__device__ __forceinline__ void project_gram_vec_tile(const JobRef *__restrict__ lats, int bx, int gx, int ly,
+                                                      int force, int which, double *red) {
     constexpr int NG = MAXK * (MAXK + 1) / 2;
     constexpr int NGK = KM * (KM + 1) / 2;
     constexpr int VL = VLEN<R>;
@@ -1453,8 +1489,7 @@ __global__ void __launch_bounds__(NT) k_project_gram_vec(const JobRef *__restric
     constexpr int NWV = NT / 64;
     constexpr int RB = 2;                       // row pairs in flight per slot
     static_assert(N % VL == 0 && GPR <= 64, "rows of at most 64 vectors");
-    __shared__ double red[NGK * (NT / 64)];
-    const LatDev &L = *lats[blockIdx.y].lat;
+    const LatDev &L = *lats[ly].lat;
     const int K = L.nstates;
     const bool ortho = force || (K > 1 && L.ortho_every > 0 && ((L.step + 1) % L.ortho_every) == 0);
     const bool do_proj = !force && L.proj_mode == 1;
@@ -1467,7 +1502,7 @@ __global__ void __launch_bounds__(NT) k_project_gram_vec(const JobRef *__restric
     double acc[NGK];
 #pragma unroll
     for (int g = 0; g < NGK; ++g) acc[g] = 0.0;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tid = tile_tid(), lane = tid & 63, wv = tid >> 6;
     const int slot = lane / GPR, g = lane % GPR;
     const int gb = zr ? GPR - 1 - g : g;
     const int src_prev = slot * GPR + (g + GPR - 1) % GPR;  // lane holding group g - 1
@@ -1483,7 +1518,7 @@ __global__ void __launch_bounds__(NT) k_project_gram_vec(const JobRef *__restric
     constexpr int SLOTS = NWV * RPW;
     // units (plane x, chunk of rows), strided over the workgroups (uniform per
     // workgroup, so every lane of a wave reaches the shuffles below)
-    for (int unit = blockIdx.x; unit < N * chunks; unit += gridDim.x) {
+    for (int unit = bx; unit < N * chunks; unit += gx) {
         const int x = unit / chunks, ch = unit % chunks;
         const int xm = (axes & 1) ? mirror_idx(x, N, center) : x;
         const int y0 = ch * rpc, y1 = y0 + rpc < N ? y0 + rpc : N;
@@ -1575,7 +1610,13 @@ __global__ void __launch_bounds__(NT) k_project_gram_vec(const JobRef *__restric
         }
     }
     // slot layout l (l + 1) / 2 + j, the same for every KM
-    block_sums<NGK, NT>(acc, L.part_gram + (size_t)blockIdx.x * NG, red);
+    block_sums<NGK, NT>(acc, L.part_gram + (size_t)bx * NG, red);
+}
+
+template <typename R, int KM, int N>
+__global__ void __launch_bounds__(NT) k_project_gram_vec(const JobRef *__restrict__ lats, int force, int which) {
+    __shared__ double red[KM * (KM + 1) / 2 * (NT / 64)];
+    project_gram_vec_tile<R, KM, N>(lats, blockIdx.x, gridDim.x, blockIdx.y, force, which, red);
 }
 
 // out_i = sum_j coef[j][i] u_j (materialise the current state i), FP64 combination.

@@ -354,6 +354,12 @@ class Batch:
     def step(self, nsteps: int):
         check(self._L.itse_batch_step(self.h, int(nsteps)))
 
+    def set_persistent(self, on: bool = True):
+        """Step through the persistent kernel (one cooperative launch per call of
+        step) instead of graph replay; raises ItseError (EINVAL) for batches it does
+        not take."""
+        check(self._L.itse_batch_set_persistent(self.h, 1 if on else 0))
+
     def close(self):
         if getattr(self, "h", None):
             self._L.itse_batch_destroy(self.h)

