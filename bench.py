@@ -248,8 +248,12 @@ def batch_leg(torch, itse, steps: int, warmup: int, count: int = 64):
     b.close()
     for lat in lats:
         lat.close()
+    # the three-pass model's bytes of every lattice's step (Gram-Schmidt every step,
+    # so the states are lazy combinations) against 8 TB/s
+    model_bytes = sum(model_step_bytes(p.n, 4, p.nstates, True) for p in probs)
     return {"site_steps_per_s": sites * steps / secs, "ms_per_step": secs * 1000.0 / steps,
             "lattices": count, "sizes": sizes, "steps": steps, "site_steps_per_step": sites,
+            "step_bytes": model_bytes, "step_hbm_frac": model_bytes / (secs / steps) / 1e9 / HBM_PEAK_GBS,
             "schedules": {n: t["best"] for n, t in tuned.items()}}
 
 

@@ -88,7 +88,8 @@ def test_complex_steps(itse, orc, n, prec, kin, center, parity, moments):
     else:
         check(f"complex.steps[{n},{kin},{center}].energies", e, 2.2e-7)
         check(f"complex.steps[{n},{kin},{center}].state", st, 2.7e-6)
-        check(f"complex.steps[{n},{kin},{center}].norm", nerr, 1.6e-9)
+        # measured 1.3e-9 with FMA contraction fixed by the source (4e-10 before)
+        check(f"complex.steps[{n},{kin},{center}].norm", nerr, 5.3e-9)
     lat.close()
 
 
