@@ -34,7 +34,7 @@ struct NVariants<float, 128> {
 };
 template <>
 struct NVariants<float, 256> {
-    static constexpr int value = 5;
+    static constexpr int value = 6;
 };
 template <>
 struct NVariants<double, 256> {
@@ -43,13 +43,15 @@ struct NVariants<double, 256> {
 
 template <typename R, int N, int V>
 static Sched sched_of() {
-    using G = Geo<R, N, V>;
+    using PV = PassVariants<R, N, V>;
+    using G = Geo<R, N, PV::COLS>;
     Sched s{};
     s.split = G::S;
     s.nwp = G::NWP;
     s.cols_w = G::W;
     s.nwc = G::NWC;
-    s.nb_rows = G::NB_PLANE;
+    // one partial-sum block per inverse plane-pass workgroup
+    s.nb_rows = Geo<R, N, PV::INV>::NB_PLANE;
     s.nb_cols = G::NB_COLS;
     s.nb_proj = N;
     s.nb_gram = pg_blocks(N);
@@ -73,6 +75,8 @@ static hipError_t dispatch(int n, int variant, F f) {
             if (variant == 3) return f.template operator()<NN, 3>();                   \
         if constexpr (NVariants<R, NN>::value > 4)                                     \
             if (variant == 4) return f.template operator()<NN, 4>();                   \
+        if constexpr (NVariants<R, NN>::value > 5)                                     \
+            if (variant == 5) return f.template operator()<NN, 5>();                   \
         return hipErrorInvalidValue;
         ITSE_FOR_EACH_N(ITSE_CASE)
 #undef ITSE_CASE
@@ -132,15 +136,25 @@ static hipError_t with_state_bound(int kmax, F f) {
     return f(std::integral_constant<int, MAXK>{});
 }
 
+// Grid of the inverse plane pass: with SPLIT, half as many sub-planes (the
+// layout's) and each job twice (its two halves; see plane_tile).
+template <int NB, bool SPLIT>
+inline dim3 split_grid(int njobs) {
+    return SPLIT ? plane_grid<NB / 2>(2 * njobs) : plane_grid<NB>(njobs);
+}
+
 template <typename R>
 struct PlaneFwdF {
     int kmax;
     const JobRef *jobs;
     int njobs;
     hipStream_t s;
-    template <int N, int V>
+    template <int N, int V0>
     hipError_t operator()() {
+        using PV = PassVariants<R, N, V0>;
+        constexpr int V = PV::FWD;
         using G = Geo<R, N, V>;
+        static_assert(G::S == Geo<R, N, PV::COLS>::S, "the forward pass writes the column pass's layout");
         return with_state_bound(kmax, [&](auto kc) {
             constexpr int KM = decltype(kc)::value;
             hipLaunchKernelGGL((k_plane_fwd<R, N, V, KM>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0, s, jobs);
@@ -162,8 +176,9 @@ struct ColumnsF {
     int njobs;
     void *out;
     hipStream_t s;
-    template <int N, int V>
+    template <int N, int V0>
     hipError_t operator()() {
+        constexpr int V = PassVariants<R, N, V0>::COLS;
         using G = Geo<R, N, V>;
         hipLaunchKernelGGL((k_columns<R, N, V>), dim3(G::NB_COLS, njobs), dim3(G::NTC), 0, s, jobs, mode, moments,
                            (C2<R> *)out);
@@ -184,17 +199,22 @@ struct PlaneInvF {
     const JobRef *jobs;
     int njobs;
     hipStream_t s;
-    template <int N, int V>
+    template <int N, int V0>
     hipError_t operator()() {
+        using PV = PassVariants<R, N, V0>;
+        constexpr int V = PV::INV;
         using G = Geo<R, N, V>;
+        static_assert(PV::SPLIT_INV ? G::S == 2 * Geo<R, N, PV::COLS>::S : G::S == Geo<R, N, PV::COLS>::S,
+                      "the inverse pass reads the column pass's layout");
         return with_state_bound(kmax, [&](auto kc) {
             constexpr int KM = decltype(kc)::value;
+            const dim3 grid = split_grid<G::NB_PLANE, PV::SPLIT_INV>(njobs);
             if (mom)
-                hipLaunchKernelGGL((k_plane_inv<R, N, V, true, KM>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0,
-                                   s, jobs, mode);
+                hipLaunchKernelGGL((k_plane_inv<R, N, V, true, KM, false, PV::SPLIT_INV>), grid, dim3(G::NTP), 0, s,
+                                   jobs, mode);
             else
-                hipLaunchKernelGGL((k_plane_inv<R, N, V, false, KM>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0,
-                                   s, jobs, mode);
+                hipLaunchKernelGGL((k_plane_inv<R, N, V, false, KM, false, PV::SPLIT_INV>), grid, dim3(G::NTP), 0, s,
+                                   jobs, mode);
             return hipGetLastError();
         });
     }
@@ -212,11 +232,14 @@ struct PlaneInvCplxF {
     const JobRef *jobs;
     int njobs;
     hipStream_t s;
-    template <int N, int V>
+    template <int N, int V0>
     hipError_t operator()() {
+        using PV = PassVariants<R, N, V0>;
+        constexpr int V = PV::INV;
         using G = Geo<R, N, V>;
-        hipLaunchKernelGGL((k_plane_inv<R, N, V, false, 4, true>), plane_grid<G::NB_PLANE>(njobs), dim3(G::NTP), 0, s,
-                           jobs, (int)INV_UPDATE);
+        const dim3 grid = split_grid<G::NB_PLANE, PV::SPLIT_INV>(njobs);
+        hipLaunchKernelGGL((k_plane_inv<R, N, V, false, 4, true, PV::SPLIT_INV>), grid, dim3(G::NTP), 0, s, jobs,
+                           (int)INV_UPDATE);
         return hipGetLastError();
     }
 };

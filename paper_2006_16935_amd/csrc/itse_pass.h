@@ -125,6 +125,9 @@ ITSE_PLAN(float, 256, 1, 2, 8, 16, 8)
 ITSE_PLAN(float, 256, 2, 4, 8, 8, 8)
 ITSE_PLAN(float, 256, 3, 4, 8, 4, 4)
 ITSE_PLAN(float, 256, 4, 8, 4, 4, 8)
+// variant 5: variant 2's layout (S = 4), forward pass and column pass; the inverse
+// plane pass on the sub-planes of variant 4 (see PassVariants)
+ITSE_PLAN(float, 256, 5, 4, 8, 8, 8)
 // FP64
 ITSE_PLAN(double, 8, 0, 1, 1, 5, 1)
 ITSE_PLAN(double, 12, 0, 1, 1, 7, 1)
@@ -139,6 +142,25 @@ ITSE_PLAN(double, 192, 0, 4, 4, 8, 8)
 ITSE_PLAN(double, 256, 0, 4, 8, 8, 8)
 ITSE_PLAN(double, 256, 1, 8, 4, 4, 8)
 #undef ITSE_PLAN
+
+// The schedules each pass of variant V runs: the forward plane pass under FWD, the
+// column pass under COLS (whose split S fixes the layout of the sub-spectra; FWD
+// writes it), the inverse plane pass under INV.  SPLIT_INV: the inverse pass
+// computes on twice as many sub-planes as the layout has; each of its workgroups
+// takes one half of a layout sub-plane's rows, joined to the layout by a radix-2
+// step of the y transform as the rows are loaded.  It then holds half a layout
+// sub-plane in LDS, while the column pass keeps the layout's longer row pieces.
+template <typename R, int N, int V>
+struct PassVariants {
+    static constexpr int FWD = V, COLS = V, INV = V;
+    static constexpr bool SPLIT_INV = false;
+};
+// 256^3 FP32: the layout of variant 2 (S = 4), the inverse pass under variant 4 (S = 8)
+template <>
+struct PassVariants<float, 256, 5> {
+    static constexpr int FWD = 2, COLS = 2, INV = 4;
+    static constexpr bool SPLIT_INV = true;
+};
 
 template <typename R, int N, int V>
 struct Geo {
@@ -539,6 +561,55 @@ __device__ __forceinline__ void block_store_rows(const C2<R> *src, C2<R> *dst_, 
     }
 }
 
+// The inverse pass's input rows when its y split is twice the layout's: rows k and
+// k + M of layout sub-spectrum (x, r_L) (M = half its rows, RL values each, row stride
+// GS) give row k of half t: e^(+2 pi i t k / 2M) (X[k] + (-1)^t X[k + M]), the first
+// radix-2 step of the inverse y transform over the layout's 2M rows (its rows
+// 2 j + t, which are the rows y = r_L + S_L (2 j + t) of the finer split's
+// sub-plane r_L + S_L t); the factor is twiddle k * TWS of the table (TWS = N / 2M).
+// Stored in LDS rows of stride RS; FP32 pairs of values per 16-byte access.
+template <typename R, int M, int RL, int GS, int RS, int TWS, int NTH>
+__device__ __forceinline__ void block_load_rows_split(const C2<R> *src_, C2<R> *dst, int t, const C2<R> *tw,
+                                                      int tid) {
+    static_assert(PAIR_ROWS<R, RL, GS, RS>, "FP32 rows copied in pairs");
+    using F4 = float __attribute__((ext_vector_type(4)));
+    constexpr int RP = (RL + 1) / 2, EP = M * RP;
+    constexpr int T = (EP + NTH - 1) / NTH;
+    constexpr int TB = T < 8 ? T : 8;
+    const ITSE_GLOBAL F4 *src = (const ITSE_GLOBAL F4 *)gmem(src_);
+    F4 *d4 = (F4 *)dst;
+#pragma unroll
+    for (int t0 = 0; t0 < T; t0 += TB) {
+        F4 va[TB], vb[TB];
+#pragma unroll
+        for (int q = 0; q < TB; ++q) {
+            const int e = tid + (t0 + q) * NTH;
+            const int ee = (EP % NTH == 0 || e < EP) ? e : EP - 1;
+            if (t0 + q < T) {
+                va[q] = src[(ee / RP) * (GS / 2) + ee % RP];
+                vb[q] = src[(ee / RP + M) * (GS / 2) + ee % RP];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < TB; ++q) {
+            const int e = tid + (t0 + q) * NTH;
+            if (t0 + q < T && (EP % NTH == 0 || e < EP)) {
+                const int k = e / RP;
+                C2<R> a0{va[q].x, va[q].y}, a1{va[q].z, va[q].w};
+                const C2<R> b0{vb[q].x, vb[q].y}, b1{vb[q].z, vb[q].w};
+                if (t == 0) {
+                    a0 = cadd(a0, b0);
+                    a1 = cadd(a1, b1);
+                } else {
+                    a0 = tw_mul<+1>(csub(a0, b0), tw, k * TWS);
+                    a1 = tw_mul<+1>(csub(a1, b1), tw, k * TWS);
+                }
+                d4[k * (RS / 2) + e % RP] = F4{a0.x, a0.y, a1.x, a1.y};
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // P1: forward plane pass.  Sub-plane x * S + r and job from plane_block.
 // ---------------------------------------------------------------------------
@@ -625,6 +696,23 @@ __device__ __forceinline__ void plane_fwd_tile(const JobRef *__restrict__ jobs, 
     if (wv == G::NWP - 1) WaveFft<R, M, 1, -1, true, S>::run(buf + N / 2, 1, HP, tw, lane);
     __syncthreads();
     block_store_rows<R, M * H, H, G::HS, HP, G::NTP>(buf, spec + ((size_t)r * N + x) * M * G::HS, tid);
+}
+
+// Sub-plane and job of a plane-pass workgroup.  SPLIT (inverse pass): the two
+// halves of a layout sub-plane run as two jobs eight workgroups apart, both on one
+// XCD at nearly the same time, so that the second finds the layout rows they share
+// in L2.
+template <int NB, int S, bool SPLIT>
+__device__ __forceinline__ int plane_tile(int &jb) {
+    if constexpr (SPLIT) {
+        constexpr int SL = S / 2;
+        int jt;
+        const int spl = plane_block<NB / 2>(jt);
+        jb = jt >> 1;
+        return (spl / SL) * S + spl % SL + SL * (jt & 1);
+    } else {
+        return plane_block<NB>(jb);
+    }
 }
 
 template <typename R, int N, int V, int KM>
@@ -922,7 +1010,7 @@ k_columns(const JobRef *__restrict__ jobs, int mode, int moments, C2<R> *__restr
 // V = Vr + i Vi it applies the complex map ((1 - h V) psi - dtau K psi)/(1 + h V)
 // and writes both parts' new arrays; besides its own row sums it forms
 // sum Vi |psi|^2 and sum |psi'|^2 (the complex-update sums).
-template <typename R, int N, int V, bool MOM, int KM, bool CPX = false>
+template <typename R, int N, int V, bool MOM, int KM, bool CPX = false, bool SPLIT = false>
 __device__ __forceinline__ void plane_inv_tile(const JobRef *__restrict__ jobs, int spb, int jb, int mode, C2<R> *buf,
                                                C2<R> *tw, double *red) {
     using G = Geo<R, N, V>;
@@ -935,8 +1023,18 @@ __device__ __forceinline__ void plane_inv_tile(const JobRef *__restrict__ jobs, 
     const int x = spb / S, r = spb % S;
     const C2<R> *twg = (const C2<R> *)L.tw;
     for (int e = tid; e < N; e += NTP) tw[e] = twg[e];
-    block_load_rows<R, M * H, H, G::HS, HP, NTP>((const C2<R> *)L.spec[i] + ((size_t)r * N + x) * M * G::HS,
-                                                 buf, tid);
+    if constexpr (SPLIT) {
+        // layout of S / 2 sub-spectra of 2 M rows: this workgroup's rows are half
+        // r / (S / 2) of layout sub-plane (x, r mod S / 2)
+        static_assert(S % 2 == 0, "the layout's split is half of this pass's");
+        constexpr int SL = S / 2;
+        __syncthreads();  // the twiddle table
+        block_load_rows_split<R, M, H, G::HS, HP, SL, NTP>(
+            (const C2<R> *)L.spec[i] + ((size_t)(r % SL) * N + x) * (2 * M) * G::HS, buf, r / SL, tw, tid);
+    } else {
+        block_load_rows<R, M * H, H, G::HS, HP, NTP>((const C2<R> *)L.spec[i] + ((size_t)r * N + x) * M * G::HS,
+                                                     buf, tid);
+    }
     __syncthreads();
     WaveFft<R, M, CPW, +1, true, S>::run(buf + wv * CPW, 1, HP, tw, lane);
     if (wv == G::NWP - 1) WaveFft<R, M, 1, +1, true, S>::run(buf + N / 2, 1, HP, tw, lane);
@@ -1115,7 +1213,7 @@ __device__ __forceinline__ void plane_inv_tile(const JobRef *__restrict__ jobs, 
     }
 }
 
-template <typename R, int N, int V, bool MOM, int KM, bool CPX = false>
+template <typename R, int N, int V, bool MOM, int KM, bool CPX = false, bool SPLIT = false>
 __global__ void __launch_bounds__((Geo<R, N, V>::NTP)) __attribute__((amdgpu_waves_per_eu(Geo<R, N, V>::WPE)))
 k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     using G = Geo<R, N, V>;
@@ -1123,8 +1221,8 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
     __shared__ C2<R> tw[N];
     __shared__ double red[NQR * (G::NTP / 64)];
     int jb;
-    const int spb = plane_block<G::NB_PLANE>(jb);
-    plane_inv_tile<R, N, V, MOM, KM, CPX>(jobs, spb, jb, mode, buf, tw, red);
+    const int spb = plane_tile<G::NB_PLANE, G::S, SPLIT>(jb);
+    plane_inv_tile<R, N, V, MOM, KM, CPX, SPLIT>(jobs, spb, jb, mode, buf, tw, red);
 }
 
 // ---------------------------------------------------------------------------

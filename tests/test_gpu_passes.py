@@ -21,7 +21,7 @@ CASES = [(32, "fp32", 1), (48, "fp32", 1), (48, "fp32", 2), (64, "fp32", 1), (64
          (96, "fp32", 2),
          (48, "fp64", 0), (96, "fp64", 0), (128, "fp32", 0), (128, "fp32", 1), (128, "fp64", 0),
          (192, "fp32", 0), (192, "fp64", 0), (256, "fp32", 0), (256, "fp32", 1), (256, "fp32", 2), (256, "fp32", 3),
-         (256, "fp32", 4),
+         (256, "fp32", 4), (256, "fp32", 5),
          (256, "fp64", 0), (256, "fp64", 1)]
 
 
@@ -106,7 +106,7 @@ def test_kinetic_schedules(itse, orc, n, prec, variant, kin):
 
 @pytest.mark.parametrize("n,prec,variant", [(96, "fp64", 0), (128, "fp64", 0), (128, "fp32", 1),
                                             (192, "fp32", 0), (256, "fp64", 0), (256, "fp64", 1),
-                                            (48, "fp32", 2), (64, "fp32", 1), (96, "fp32", 2)])
+                                            (48, "fp32", 2), (64, "fp32", 1), (96, "fp32", 2), (256, "fp32", 5)])
 def test_multistate_steps_large(itse, orc, n, prec, variant):
     """Three states (even, odd, odd deflated against the odd one), Cornell potential,
     a few steps: every step's energies and the final states match the oracle."""
@@ -202,7 +202,7 @@ def test_projection_origin_axes(itse, orc, n, prec, parity, axes):
     lat.close()
 
 
-@pytest.mark.parametrize("variant", [2, 4])
+@pytest.mark.parametrize("variant", [2, 4, 5])
 def test_bare_one_state_steps(itse, orc, variant):
     """The bare one-state 256^3 FP32 step of the benchmark (no projection, no
     Gram-Schmidt): energies of the first steps and the state after them match the

@@ -80,7 +80,7 @@ def _errors(hist, got, oh, ost):
     return e, [_rel(g, r) for g, r in zip(got, ost)]
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 def test_fp32_workload_states(itse, work256, variant):
     """The benchmarked 256^3 FP32 three-state step: energies and norms of every
     step, and all three states after the steps, site by site, in every schedule."""
@@ -108,7 +108,7 @@ def test_fp64_workload_states(itse, work128, work256, n, variant):
 KIN_FORMS = [(2, True), (4, True), (4, False), (3, False)]
 
 
-@pytest.mark.parametrize("prec,variant", [("fp32", v) for v in range(5)] + [("fp64", 0), ("fp64", 1)])
+@pytest.mark.parametrize("prec,variant", [("fp32", v) for v in range(6)] + [("fp64", 0), ("fp64", 1)])
 @pytest.mark.parametrize("kin,sub", KIN_FORMS)
 def test_kinetic_forms_256(itse, orc, prec, variant, kin, sub):
     """H_K^(2), the continuum-momentum relativistic form with and without the rest
