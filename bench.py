@@ -219,8 +219,12 @@ def batch_leg(torch, itse, steps: int, warmup: int, count: int = 64):
     import synth
     probs = synth.batch_problems(count=count, seed=0, nstates=2)
     # schedules per size picked by the library's autotuner before the lattices are
-    # created (a lattice takes the schedule current at its creation)
-    tuned = {n: json.loads(itse.autotune(n, "fp32")) for n in sorted({p.n for p in probs})}
+    # created (a lattice takes the schedule current at its creation): each size timed
+    # as a batch of as many lattices as the mix holds of it
+    sizes = {}
+    for p in probs:
+        sizes[p.n] = sizes.get(p.n, 0) + 1
+    tuned = {n: json.loads(itse.autotune_batch(n, "fp32", c, 2)) for n, c in sorted(sizes.items())}
     lats = []
     for p in probs:
         lat = itse.Lattice(p.n, p.a, p.mass, p.dtau, kin=p.kin, subtract_rest_mass=p.subtract_rest_mass,
@@ -242,9 +246,6 @@ def batch_leg(torch, itse, steps: int, warmup: int, count: int = 64):
     for lat in lats:
         lat.sync()
     sites = sum(p.n ** 3 * p.nstates for p in probs)
-    sizes = {}
-    for p in probs:
-        sizes[p.n] = sizes.get(p.n, 0) + 1
     b.close()
     for lat in lats:
         lat.close()

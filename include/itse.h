@@ -341,6 +341,17 @@ itse_status itse_batch_set_persistent(itse_batch *b, int on);
  * `json` (optional) receives the timings ("times_ms", "times_ms_one_state") and
  * the choices ("best", "best_one_state"). */
 itse_status itse_autotune(int n, int precision, void *hip_stream, char *json, size_t json_len);
+/* The same for lattices stepped together: times a batch of `count` lattices of
+ * (n, precision) with `nstates` states each (Gram-Schmidt every step) under every
+ * schedule and keeps the fastest for that kind of lattice (several states, or one)
+ * -- with many lattices in a batch there is parallelism enough without finer
+ * splits, so the choice can differ from itse_autotune's.  `json` receives
+ * "times_ms" (per step of the batch) and "best".  Allocates and frees the
+ * lattices it times (about count times one lattice's footprint); errors:
+ * ITSE_EINVAL (count < 1, nstates outside 1..ITSE_MAX_STATES, unknown shape),
+ * ITSE_ENOMEM, ITSE_EDEVICE. */
+itse_status itse_autotune_batch(int n, int precision, int count, int nstates, void *hip_stream, char *json,
+                                size_t json_len);
 /* Description of the current multi-state schedule, with "variant_one_state". */
 itse_status itse_schedule_get(int n, int precision, char *json, size_t json_len);
 /* Set the schedule of both kinds of lattice; errors: ITSE_EINVAL for an unknown

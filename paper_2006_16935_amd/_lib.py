@@ -131,6 +131,7 @@ def load():
         "itse_batch_set_persistent": ([vp, ip], ip),
         "itse_batch_destroy": ([vp], ip),
         "itse_autotune": ([ip, ip, vp, ctypes.c_char_p, ctypes.c_size_t], ip),
+        "itse_autotune_batch": ([ip, ip, ip, ip, vp, ctypes.c_char_p, ctypes.c_size_t], ip),
         "itse_schedule_get": ([ip, ip, ctypes.c_char_p, ctypes.c_size_t], ip),
         "itse_schedule_set": ([ip, ip, ip], ip),
         "itse_schedule_set_states": ([ip, ip, ip, ip], ip),

@@ -340,7 +340,10 @@ extern "C" itse_status itse_batch_destroy(itse_batch *B) {
 // Mean time (ms) of a step of a lattice of `nstates` states under schedule
 // variant v: synthetic states, parity +, -, - and Gram-Schmidt every step for
 // several states (every kernel of a step runs), the bare step for one state.
-static itse_status time_variant(int n, int precision, int v, int nstates, void *stream, float *out_ms) {
+// Time `count` lattices of (n, precision) with `nstates` states stepped under
+// schedule v (one lattice: itse_step; several: one batch).  Mean ms per step.
+static itse_status time_variant(int n, int precision, int v, int nstates, void *stream, float *out_ms,
+                                int count = 1) {
     {
         std::lock_guard<std::mutex> lk(g_sched_mu);
         g_sched[{n, precision, nstates == 1 ? 1 : 0}] = v;
@@ -355,15 +358,11 @@ static itse_status time_variant(int n, int precision, int v, int nstates, void *
     d.precision = precision;
     d.center = ITSE_CENTER_ORIGIN;
     d.nstates = nstates;
-    itse_lattice *L = nullptr;
-    itse_status st = itse_create(&d, stream, nullptr, nullptr, nullptr, &L);
-    if (st) return st;
+    std::vector<itse_lattice *> lats(count, nullptr);
+    itse_batch *B = nullptr;
+    itse_status st = ITSE_OK;
     const size_t n3 = (size_t)n * n * n;
     std::vector<double> psi(n3);
-    for (int i = 0; i < d.nstates && !st; ++i) {
-        for (size_t e = 0; e < n3; ++e) psi[e] = std::sin(0.37 * (double)(e % 100003) * (i + 1)) + 0.1 * i;
-        st = itse_set_state(L, i, psi.data(), ITSE_DTYPE_F64, 0);
-    }
     itse_step_opts o{};
     o.ortho_every = nstates > 1 ? 1 : 0;
     if (nstates > 1) {
@@ -371,7 +370,17 @@ static itse_status time_variant(int n, int precision, int v, int nstates, void *
         for (int i = 1; i < nstates; ++i) o.parity[i] = -1;
     }
     for (int i = 0; i < ITSE_MAX_STATES; ++i) o.axes[i] = 7;
-    if (!st) st = itse_step(L, 3, &o);
+    for (int c = 0; c < count && !st; ++c) {
+        st = itse_create(&d, stream, nullptr, nullptr, nullptr, &lats[c]);
+        for (int i = 0; i < d.nstates && !st; ++i) {
+            for (size_t e = 0; e < n3; ++e) psi[e] = std::sin(0.37 * (double)(e % 100003) * (i + 1)) + 0.1 * i;
+            st = itse_set_state(lats[c], i, psi.data(), ITSE_DTYPE_F64, 0);
+        }
+        if (!st) st = itse_set_step_opts(lats[c], &o);
+    }
+    if (!st && count > 1) st = itse_batch_create(count, lats.data(), stream, &B);
+    auto steps = [&](int k) { return B ? itse_batch_step(B, k) : itse_step(lats[0], k, nullptr); };
+    if (!st) st = steps(3);
     const int reps = n >= 192 ? 10 : 30;
     float ms = 1e30f;
     for (int trial = 0; trial < 2 && !st; ++trial) {
@@ -379,7 +388,7 @@ static itse_status time_variant(int n, int precision, int v, int nstates, void *
         hipError_t he = hipEventCreate(&e0);
         if (he == hipSuccess) he = hipEventCreate(&e1);
         if (he == hipSuccess) he = hipEventRecord(e0, (hipStream_t)stream);
-        if (he == hipSuccess) st = itse_step(L, reps, nullptr);
+        if (he == hipSuccess) st = steps(reps);
         if (he == hipSuccess && !st) he = hipEventRecord(e1, (hipStream_t)stream);
         if (he == hipSuccess && !st) he = hipEventSynchronize(e1);
         float t = 0.f;
@@ -389,8 +398,11 @@ static itse_status time_variant(int n, int precision, int v, int nstates, void *
         if (he != hipSuccess && !st) st = fail(ITSE_EDEVICE, "autotune timing: %s", hipGetErrorString(he));
         if (!st) ms = std::min(ms, t);
     }
-    if (!st) st = itse_sync(L);
-    itse_destroy(L);
+    for (auto *L : lats)
+        if (L && !st) st = itse_sync(L);
+    if (B) itse_batch_destroy(B);
+    for (auto *L : lats)
+        if (L) itse_destroy(L);
     *out_ms = ms / reps;
     return st;
 }
@@ -418,6 +430,36 @@ extern "C" itse_status itse_autotune(int n, int precision, void *stream, char *j
         g_sched[{n, precision, one}] = best[one];
     }
     rep += ", \"best\": " + std::to_string(best[0]) + ", \"best_one_state\": " + std::to_string(best[1]) + "}";
+    if (json && len) snprintf(json, len, "%s", rep.c_str());
+    return ITSE_OK;
+}
+
+extern "C" itse_status itse_autotune_batch(int n, int precision, int count, int nstates, void *stream, char *json,
+                                           size_t len) {
+    if (!prec_supported(n, precision)) return fail(ITSE_EINVAL, "n = %d not supported", n);
+    if (count < 1) return fail(ITSE_EINVAL, "count = %d", count);
+    if (nstates < 1 || nstates > MAXK) return fail(ITSE_EINVAL, "nstates = %d", nstates);
+    const int nv = precision == ITSE_FP32 ? Launch<float>::variants(n) : Launch<double>::variants(n);
+    std::string rep = "{\"n\": " + std::to_string(n) + ", \"precision\": " + std::to_string(precision) +
+                      ", \"count\": " + std::to_string(count) + ", \"nstates\": " + std::to_string(nstates) +
+                      ", \"times_ms\": [";
+    int best = 0;
+    float best_ms = 1e30f;
+    for (int v = 0; v < nv; ++v) {
+        float ms = 0.f;
+        itse_status st = time_variant(n, precision, v, nstates, stream, &ms, count);
+        if (st) return st;
+        rep += (v ? ", " : "") + std::to_string(ms);
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = v;
+        }
+    }
+    rep += "], \"best\": " + std::to_string(best) + "}";
+    {
+        std::lock_guard<std::mutex> lk(g_sched_mu);
+        g_sched[{n, precision, nstates == 1 ? 1 : 0}] = best;
+    }
     if (json && len) snprintf(json, len, "%s", rep.c_str());
     return ITSE_OK;
 }

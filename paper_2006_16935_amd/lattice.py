@@ -380,6 +380,16 @@ def autotune(n: int, precision: str = "fp32", stream=None) -> str:
     return buf.value.decode()
 
 
+def autotune_batch(n: int, precision: str = "fp32", count: int = 1, nstates: int = 2, stream=None) -> str:
+    """Time every schedule of (n, precision) on a batch of `count` lattices with
+    `nstates` states and keep the fastest for that kind of lattice; JSON report."""
+    L = _lib.load()
+    sp, _ = _stream_handle(stream)
+    buf = ctypes.create_string_buffer(4096)
+    check(L.itse_autotune_batch(int(n), _PREC[precision], int(count), int(nstates), sp, buf, 4096))
+    return buf.value.decode()
+
+
 def schedule(n: int, precision: str = "fp32") -> str:
     L = _lib.load()
     buf = ctypes.create_string_buffer(1024)

@@ -187,3 +187,30 @@ def test_server_converged_eigenpair_certified(itse, orc):
     cert = orc.certify(_olat(orc, p), psi, p.potential_array(np.float64))
     assert abs(cert["energy"] - r["energy"][0]) <= 1e-10 * abs(r["energy"][0])
     assert cert["resid"] < 1e-5
+
+
+def test_autotuners_report_and_set_schedules(itse):
+    """itse_autotune times every schedule of a size on a three-state and a one-state
+    step and keeps the fastest of each; itse_autotune_batch times a batch of the
+    given count and state number and keeps the fastest for that kind of lattice.
+    Bad counts and state numbers are refused."""
+    import json
+    n = 48
+    nv = itse.schedule_variants(n, "fp32")
+    try:
+        single = json.loads(itse.autotune(n, "fp32"))
+        assert len(single["times_ms"]) == nv and len(single["times_ms_one_state"]) == nv
+        assert all(t > 0 for t in single["times_ms"] + single["times_ms_one_state"])
+        assert single["times_ms"][single["best"]] == min(single["times_ms"])
+        cur = json.loads(itse.schedule(n, "fp32"))
+        assert cur["variant"] == single["best"] and cur["variant_one_state"] == single["best_one_state"]
+        batch = json.loads(itse.autotune_batch(n, "fp32", 6, 2))
+        assert batch["count"] == 6 and batch["nstates"] == 2 and len(batch["times_ms"]) == nv
+        assert batch["times_ms"][batch["best"]] == min(batch["times_ms"])
+        assert json.loads(itse.schedule(n, "fp32"))["variant"] == batch["best"]
+        with pytest.raises(itse.ItseError, match="EINVAL"):
+            itse.autotune_batch(n, "fp32", 0, 2)
+        with pytest.raises(itse.ItseError, match="EINVAL"):
+            itse.autotune_batch(n, "fp32", 2, 0)
+    finally:
+        itse.set_schedule(n, "fp32", 0)
