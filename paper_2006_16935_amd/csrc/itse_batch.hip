@@ -273,6 +273,14 @@ extern "C" itse_status itse_batch_step(itse_batch *B, int nsteps) {
         if (needs != B->groups[gi].needs) changed = true;
         B->groups[gi].needs = needs;
     }
+    // cached graphs of an older set of passes are dropped here, before either path,
+    // so that a change made while stepping persistently is not missed later
+    if (changed && (B->graph1 || B->graphN)) {
+        HIPCHK(hipStreamSynchronize(B->stream));
+        if (B->graph1) HIPCHK(hipGraphExecDestroy(B->graph1));
+        if (B->graphN) HIPCHK(hipGraphExecDestroy(B->graphN));
+        B->graph1 = B->graphN = nullptr;
+    }
     // the persistent kernel, when the steps need no per-state projection pass and no
     // position moments (else the graph path)
     bool persist = B->persistent;
@@ -293,12 +301,6 @@ extern "C" itse_status itse_batch_step(itse_batch *B, int nsteps) {
         }
         HIPCHK(hipEventDestroy(done));
         return ITSE_OK;
-    }
-    if (changed && (B->graph1 || B->graphN)) {
-        HIPCHK(hipStreamSynchronize(B->stream));
-        if (B->graph1) HIPCHK(hipGraphExecDestroy(B->graph1));
-        if (B->graphN) HIPCHK(hipGraphExecDestroy(B->graphN));
-        B->graph1 = B->graphN = nullptr;
     }
     const int chunk = ITSE_GRAPH_CHUNK;
     if (nsteps >= chunk && !B->graphN) {

@@ -148,3 +148,32 @@ def test_persistent_rejects_other_batches(itse):
         assert lat.step_count == 2
         b.close()
         lat.close()
+
+
+def test_options_changed_during_persistent_steps(itse):
+    """Options that change the step's passes while the batch steps persistently
+    (here Gram-Schmidt switched on) also reach the graph path afterwards: graphs
+    captured before the change are not replayed.  Bitwise equal to stepping alone
+    with the same sequence of options."""
+    probs = synth.batch_problems(count=5, seed=51, nstates=2)
+    alone, batched = _pairs(itse, probs, 1)
+    for lat in alone + batched:
+        lat.set_options(ortho_every=0)
+    batch = itse.Batch(batched)
+    for lat in alone:
+        lat.step(3)
+    batch.step(3)                      # graphs captured without the Gram pass
+    for lat in alone + batched:
+        lat.set_options(ortho_every=1)
+    batch.set_persistent(True)
+    for lat in alone:
+        lat.step(4)
+    batch.step(4)                      # persistent, with the Gram pass
+    batch.set_persistent(False)
+    for lat in alone:
+        lat.step(5)
+    batch.step(5)                      # graph path again: must include the Gram pass
+    _assert_bitwise(probs, alone, batched)
+    batch.close()
+    for lat in alone + batched:
+        lat.close()
