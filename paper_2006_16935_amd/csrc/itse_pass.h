@@ -1264,13 +1264,18 @@ struct FdGeo {
 };
 
 // psi = sum_(j<=i) c_j u_j at one vector (FP64 combination, rounded once); KM
-// bounds the number of states (i < KM).
+// bounds the number of states (i < KM).  Split into the loads and the
+// combination, so that a caller can issue the loads early and combine only when
+// the values are needed (the combination waits for them).
 template <typename R, int KM>
-__device__ __forceinline__ Vec<R> lazy_vec(const LatView<R, KM> &vw, size_t off, bool ok) {
-    constexpr int VL = VLEN<R>;
-    Vec<R> u[KM];
+__device__ __forceinline__ void lazy_vec_load(const LatView<R, KM> &vw, size_t off, bool ok, Vec<R> (&u)[KM]) {
 #pragma unroll
     for (int j = 0; j < KM; ++j) u[j] = (j <= vw.i && ok) ? *(const ITSE_GLOBAL Vec<R> *)(vw.u[j] + off) : Vec<R>{};
+}
+
+template <typename R, int KM>
+__device__ __forceinline__ Vec<R> lazy_vec_combine(const LatView<R, KM> &vw, const Vec<R> (&u)[KM], bool ok) {
+    constexpr int VL = VLEN<R>;
     Vec<R> out;
 #pragma unroll
     for (int k = 0; k < VL; ++k) {
@@ -1283,16 +1288,26 @@ __device__ __forceinline__ Vec<R> lazy_vec(const LatView<R, KM> &vw, size_t off,
     return out;
 }
 
+template <typename R, int KM>
+__device__ __forceinline__ Vec<R> lazy_vec(const LatView<R, KM> &vw, size_t off, bool ok) {
+    Vec<R> u[KM];
+    lazy_vec_load<R, KM>(vw, off, ok, u);
+    return lazy_vec_combine<R, KM>(vw, u, ok);
+}
+
 template <typename R, int N, int KM>
 __global__ void __launch_bounds__(NT) k_fdtd(const JobRef *__restrict__ jobs, int mode) {
     using G = FdGeo<R, N>;
     constexpr int VL = G::VL, GPR = G::GPR, TY = G::TY, XS = G::XS, TV = G::TV;
     __shared__ __attribute__((aligned(16))) R pl[(TY + 2) * N];
     __shared__ double red[NQR * (NT / 64)];
-    // flat grid (tile, segment, job); consecutive tiles share halo rows: same XCD
-    const int nb = G::NB * (int)(gridDim.x / G::NB);
-    const int b = xcd_local_index(blockIdx.x, nb);
-    const int wg = b % G::NB, jb = b / G::NB;
+    // flat grid over (segment, tile, job), the job fastest, in XCD-contiguous
+    // ranges: the jobs of one tile (which read the same lower states' arrays and V)
+    // and neighbouring tiles (which share halo rows) run on the same XCD at nearly
+    // the same time, so the repeated reads come from its L2
+    const int nj = (int)(gridDim.x / G::NB);
+    const int b = xcd_local_index(blockIdx.x, G::NB * nj);
+    const int jb = b % nj, wg = b / nj;
     const int tile = wg % G::TILES, seg = wg / G::TILES;
     const int y0 = tile * TY, x0 = seg * XS;
     const JobRef job = jobs[jb];
@@ -1320,34 +1335,55 @@ __global__ void __launch_bounds__(NT) k_fdtd(const JobRef *__restrict__ jobs, in
     auto off = [&](int xx, int yy, int zz) { return ((size_t)xx * N + yy) * N + zz; };
     // the planes before the first and after the last are outside the box for
     // x0 = 0 and x0 + XS = N, else real planes of the lattice
+    // One-state jobs load the centre rows two planes ahead (plane xx + 2 in
+    // iteration xx, combined after the stencil, so that the loads' latency overlaps
+    // it).  With more states the raw loads held across the stencil cost a wave per
+    // SIMD, which was slower: their centre rows are loaded one plane ahead and
+    // combined at once.
+    constexpr bool AHEAD = KM == 1;
     Vec<R> pm = lazy_vec<R, KM>(vw, off(x0 > 0 ? x0 - 1 : 0, y, z0), own && x0 > 0);
     Vec<R> pc = lazy_vec<R, KM>(vw, off(x0, y, z0), own);
+    Vec<R> pn = AHEAD ? lazy_vec<R, KM>(vw, off(x0 + 1 < N ? x0 + 1 : 0, y, z0), own && x0 + 1 < N) : Vec<R>{};
     Vec<R> hc = lazy_vec<R, KM>(vw, off(x0, hin ? hy : 0, hg * VL), hin);
     Vec<R> vc = own ? *(const ITSE_GLOBAL Vec<R> *)(v + off(x0, y, z0)) : Vec<R>{};
     double acc[NQR];
 #pragma unroll
     for (int q = 0; q < NQR; ++q) acc[q] = 0.0;
     const double cy = site_coord(y, N, center, a);
+    // the first planes' loads complete here: otherwise the compiler's wait for V
+    // inside the loop (a value loaded before it) also waits for the loads that the
+    // loop issues ahead
+    if constexpr (AHEAD) __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
 #pragma unroll 1
     for (int xx = x0; xx < x0 + XS; ++xx) {
-        // loads for the next plane
-        const bool nx = xx + 1 < N;
-        const Vec<R> pn = lazy_vec<R, KM>(vw, off(nx ? xx + 1 : 0, y, z0), own && nx);
-        const bool hnext = hin && xx + 1 < x0 + XS;
-        const Vec<R> hn = lazy_vec<R, KM>(vw, off(hnext ? xx + 1 : 0, hin ? hy : 0, hg * VL), hnext);
-        const Vec<R> vn = (own && xx + 1 < x0 + XS) ? *(const ITSE_GLOBAL Vec<R> *)(v + off(xx + 1, y, z0))
-                                                     : Vec<R>{};
+        // loads for the next iteration: plane xx + 1's halo rows and V, and the
+        // centre rows of plane xx + 2 (AHEAD) or of plane xx + 1 (needed now);
+        // planes from N on are outside the box (zero)
+        const bool more = xx + 1 < x0 + XS;
+        const bool n2 = more && xx + 2 < N;
+        Vec<R> rn[KM], rh[KM];
+        if constexpr (AHEAD) {
+            lazy_vec_load<R, KM>(vw, off(n2 ? xx + 2 : 0, y, z0), own && n2, rn);
+        } else {
+            const bool nx = xx + 1 < N;
+            pn = lazy_vec<R, KM>(vw, off(nx ? xx + 1 : 0, y, z0), own && nx);
+        }
+        const bool hnext = hin && more;
+        lazy_vec_load<R, KM>(vw, off(hnext ? xx + 1 : 0, hin ? hy : 0, hg * VL), hnext, rh);
+        Vec<R> hn{};
+        if constexpr (!AHEAD) hn = lazy_vec_combine<R, KM>(vw, rh, hnext);
+        const Vec<R> vn = (own && more) ? *(const ITSE_GLOBAL Vec<R> *)(v + off(xx + 1, y, z0)) : Vec<R>{};
         // plane xx with its halo rows into LDS
         if (own) *(Vec<R> *)&pl[(row + 1) * N + z0] = pc;
         if (hal) *(Vec<R> *)&pl[(hrow == 0 ? 0 : TY + 1) * N + hg * VL] = hc;
         __syncthreads();
+        Vec<R> un{}, kv{};
         if (own) {
             const Vec<R> ym = *(const Vec<R> *)&pl[row * N + z0];
             const Vec<R> yp = *(const Vec<R> *)&pl[(row + 2) * N + z0];
             const R zl = z0 > 0 ? pl[(row + 1) * N + z0 - 1] : (R)0;
             const R zr = z0 + VL < N ? pl[(row + 1) * N + z0 + VL] : (R)0;
             const double cx = site_coord(xx, N, center, a);
-            Vec<R> un, kv;
 #pragma unroll
             for (int k = 0; k < VL; ++k) {
                 const R left = k > 0 ? pc[k - 1] : zl;
@@ -1373,14 +1409,33 @@ __global__ void __launch_bounds__(NT) k_fdtd(const JobRef *__restrict__ jobs, in
                     acc[RQ_R2] += (cx * cx + cy * cy + cz * cz) * w2;
                 }
             }
-            if (mode == INV_UPDATE) *(ITSE_GLOBAL Vec<R> *)(u + off(xx, y, z0)) = un;
-            else if (mode >= INV_KOUT) *(ITSE_GLOBAL Vec<R> *)(kout + off(xx, y, z0)) = kv;
+            if constexpr (!AHEAD) {
+                if (mode == INV_UPDATE) *(ITSE_GLOBAL Vec<R> *)(u + off(xx, y, z0)) = un;
+                else if (mode >= INV_KOUT) *(ITSE_GLOBAL Vec<R> *)(kout + off(xx, y, z0)) = kv;
+            }
         }
-        __syncthreads();
-        pm = pc;
-        pc = pn;
-        hc = hn;
-        vc = vn;
+        if constexpr (AHEAD) {
+            // the next iteration's values (this waits for the loads), then this
+            // plane's stores, so that the wait does not include their completion
+            pm = pc;
+            pc = pn;
+            pn = lazy_vec_combine<R, KM>(vw, rn, own && n2);
+            hc = lazy_vec_combine<R, KM>(vw, rh, hnext);
+            vc = vn;
+            // keeps the stores below the combination (the compiler would hoist them)
+            asm volatile("" ::"v"(pn), "v"(hc), "v"(vc) : "memory");
+            if (own) {
+                if (mode == INV_UPDATE) *(ITSE_GLOBAL Vec<R> *)(u + off(xx, y, z0)) = un;
+                else if (mode >= INV_KOUT) *(ITSE_GLOBAL Vec<R> *)(kout + off(xx, y, z0)) = kv;
+            }
+            __syncthreads();
+        } else {
+            __syncthreads();
+            pm = pc;
+            pc = pn;
+            hc = hn;
+            vc = vn;
+        }
     }
     block_sums<NQR, NT>(acc, L.part_rows + ((size_t)i * L.nb_rows + wg) * NQR, red);
 }

@@ -78,6 +78,38 @@ def test_fdtd_multistate_steps(itse, orc, n, prec, center, parity, axes):
     lat.close()
 
 
+@pytest.mark.parametrize("n,prec,center,moments", [
+    (16, "fp64", "cell", True), (32, "fp32", "origin", False), (96, "fp32", "cell", True),
+    (128, "fp64", "origin", False),
+])
+def test_fdtd_one_state_steps(itse, orc, n, prec, center, moments):
+    """One state (the instance that loads its centre rows two planes ahead), no
+    projection: energies, norms and the state after the steps follow the oracle
+    element by element; segments of x planes start and end at the walls and inside
+    the box at these sizes."""
+    steps = 6
+    a = 0.25
+    lat = _lat(itse, n, prec, nstates=1, a=a, center=center)
+    dt = np.float32 if prec == "fp32" else np.float64
+    v = synth.potential_cornell(n, a, center, sigma=0.2, alpha=0.4).astype(dt)
+    psi = synth.random_state(n, 90 + n, dtype=dt)
+    lat.set_potential(v)
+    lat.set_state(0, psi)
+    lat.set_options(moments=moments)
+    lat.step(steps)
+    hist = lat.history(steps)
+    ostates, ohist = orc.step(_olat(orc, lat), [psi.astype(np.float64)], v.astype(np.float64), steps)
+    keys = ("energy", "norm2", "x", "r2") if moments else ("energy", "norm2")
+    e = max_rel_energy(hist, ohist, keys, floor=1.0)
+    st = _rel(lat.get_state(0), ostates[0])
+    if prec == "fp64":
+        assert e <= 1e-10 and st <= 1e-10, (e, st)
+    else:
+        check(f"fdtd.one_state[{n}].energies", e, 1.7e-7)
+        check(f"fdtd.one_state[{n}].state", st, 1.5e-6)
+    lat.close()
+
+
 def test_fdtd_large_first_steps(itse, orc):
     """256^3 FP32, three states (parity +, -, - and Gram-Schmidt), Cornell potential:
     the first steps' energies match the FP64 oracle on the same FP32 inputs."""
