@@ -304,6 +304,7 @@ hipError_t Launch<R>::fdtd(int n, int kmax, int mode, const JobRef *jobs, int nj
         const dim3 grid(FdGeo<R, NN>::NB * njobs);
         if (kmax <= 1) hipLaunchKernelGGL((k_fdtd<R, NN, 1>), grid, dim3(NT), 0, s, jobs, mode);
         else if (kmax <= 2) hipLaunchKernelGGL((k_fdtd<R, NN, 2>), grid, dim3(NT), 0, s, jobs, mode);
+        else if (kmax <= 3) hipLaunchKernelGGL((k_fdtd<R, NN, 3>), grid, dim3(NT), 0, s, jobs, mode);
         else if (kmax <= 4) hipLaunchKernelGGL((k_fdtd<R, NN, 4>), grid, dim3(NT), 0, s, jobs, mode);
         else hipLaunchKernelGGL((k_fdtd<R, NN, MAXK>), grid, dim3(NT), 0, s, jobs, mode);
         return hipGetLastError();

@@ -1335,12 +1335,12 @@ __global__ void __launch_bounds__(NT) k_fdtd(const JobRef *__restrict__ jobs, in
     auto off = [&](int xx, int yy, int zz) { return ((size_t)xx * N + yy) * N + zz; };
     // the planes before the first and after the last are outside the box for
     // x0 = 0 and x0 + XS = N, else real planes of the lattice
-    // One-state jobs load the centre rows two planes ahead (plane xx + 2 in
-    // iteration xx, combined after the stencil, so that the loads' latency overlaps
-    // it).  With more states the raw loads held across the stencil cost a wave per
-    // SIMD, which was slower: their centre rows are loaded one plane ahead and
-    // combined at once.
-    constexpr bool AHEAD = KM == 1;
+    // Instances of up to three states load the centre rows two planes ahead (plane
+    // xx + 2 in iteration xx, combined after the stencil, so that the loads' latency
+    // overlaps it).  With four or more the raw loads held across the stencil cost a
+    // wave per SIMD: their centre rows are loaded one plane ahead and combined at
+    // once.
+    constexpr bool AHEAD = KM <= 3;
     Vec<R> pm = lazy_vec<R, KM>(vw, off(x0 > 0 ? x0 - 1 : 0, y, z0), own && x0 > 0);
     Vec<R> pc = lazy_vec<R, KM>(vw, off(x0, y, z0), own);
     Vec<R> pn = AHEAD ? lazy_vec<R, KM>(vw, off(x0 + 1 < N ? x0 + 1 : 0, y, z0), own && x0 + 1 < N) : Vec<R>{};
