@@ -1087,11 +1087,12 @@ __device__ __forceinline__ void plane_inv_tile(const JobRef *__restrict__ jobs, 
     // UPFRONT (FP32 lattices and FP64 from N = 128; no moments, no complex part, up to
     // four states): every global load of a round (V and the lazy combination's
     // arrays) is issued before any of them is used, one memory round trip per round;
-    // the registers then allow two chunks per round for one state and one for more.
-    // Otherwise the arrays load one after another (each array's loads issued
-    // together), two chunks per round without moments.
+    // the registers then allow two chunks per round for one state, and for more
+    // where the plane's LDS keeps the pass at two waves per SIMD or fewer (256
+    // VGPRs); one otherwise.  Otherwise the arrays load one after another (each
+    // array's loads issued together), two chunks per round without moments.
     constexpr bool UPFRONT = (sizeof(R) == 4 || N >= 128) && !MOM && !CPX && KM <= 4;
-    using PC = PairChunks<R, N, PPW, UPFRONT ? (KM > 1 ? 1 : 2) : ((MOM || CPX) ? 1 : 2)>;
+    using PC = PairChunks<R, N, PPW, UPFRONT ? ((KM == 1 || G::WPE <= 2) ? 2 : 1) : ((MOM || CPX) ? 1 : 2)>;
     constexpr int VL = PC::VL, GG = PC::G;
     const double cx = site_coord(x, N, center, a);
     // CPX: the real part's raw array and K psi, Im V, the real part's new array
