@@ -634,6 +634,12 @@ __device__ __forceinline__ void plane_fwd_tile(const JobRef *__restrict__ jobs, 
     // rows of this wave's pairs -> packed complex rows (z along the line)
     const int p0 = wv * PPW;
     {
+        // FP64 lattices whose plane's LDS keeps the pass at two waves per SIMD or
+        // fewer (registers for a round's raw arrays): every array's loads of a round
+        // issued before any is used, one memory round trip per round.  Otherwise one
+        // array after another (FP32 under schedule 1 at 256^3 measured 2 % slower
+        // up front).
+        constexpr bool UPFRONT = sizeof(R) == 8 && G::WPE <= 2 && KM <= 4;
         using PC = PairChunks<R, N, PPW, KM <= 4 ? 4 : 2>;
         constexpr int VL = PC::VL, G = PC::G;
 #pragma unroll 1
@@ -653,7 +659,13 @@ __device__ __forceinline__ void plane_fwd_tile(const JobRef *__restrict__ jobs, 
                 lp[t] = p * LSZ + z;
             }
             R v0[G][VL], v1[G][VL];
-            lazy_rows<R, G>(vw, o0, o1, ok, v0, v1);
+            if constexpr (UPFRONT) {
+                LazyRaw<R, G, KM> raw;
+                lazy_issue<R, G>(vw, o0, o1, ok, raw);
+                lazy_combine<R, G>(vw, raw, v0, v1);
+            } else {
+                lazy_rows<R, G>(vw, o0, o1, ok, v0, v1);
+            }
 #pragma unroll
             for (int t = 0; t < G; ++t)
                 if (ok[t]) {
