@@ -1366,7 +1366,9 @@ __global__ void __launch_bounds__(NT) k_fdtd(const JobRef *__restrict__ jobs, in
     // the first planes' loads complete here: otherwise the compiler's wait for V
     // inside the loop (a value loaded before it) also waits for the loads that the
     // loop issues ahead
-    if constexpr (AHEAD) __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
+    // (CDNA s_waitcnt immediate: vmcnt in bits 3:0 and 15:14 = 0, expcnt in bits 6:4
+    // = 7 and lgkmcnt in bits 11:8 = 15, i.e. wait for vector memory only)
+    if constexpr (AHEAD) __builtin_amdgcn_s_waitcnt(0x0f70);
 #pragma unroll 1
     for (int xx = x0; xx < x0 + XS; ++xx) {
         // loads for the next iteration: plane xx + 1's halo rows and V, and the
