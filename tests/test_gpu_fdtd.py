@@ -78,6 +78,35 @@ def test_fdtd_multistate_steps(itse, orc, n, prec, center, parity, axes):
     lat.close()
 
 
+@pytest.mark.parametrize("n,prec,nstates", [(24, "fp64", 4), (32, "fp32", 4), (48, "fp64", 6), (64, "fp32", 7)])
+def test_fdtd_many_states_steps(itse, orc, n, prec, nstates):
+    """Four to seven states (the instances that load their centre rows one plane
+    ahead), Gram-Schmidt every step: energies, norms and every state after the
+    steps follow the oracle."""
+    steps = 5
+    a = 0.25
+    lat = _lat(itse, n, prec, nstates=nstates, a=a, center="origin")
+    dt = np.float32 if prec == "fp32" else np.float64
+    v = synth.potential_cornell(n, a, "origin", sigma=0.2, alpha=0.4).astype(dt)
+    states = synth.random_states(n, nstates, seed=120 + n, dtype=dt)
+    lat.set_potential(v)
+    for i, s in enumerate(states):
+        lat.set_state(i, s)
+    lat.set_options(ortho_every=1)
+    lat.step(steps)
+    hist = lat.history(steps)
+    ostates, ohist = orc.step(_olat(orc, lat), [s.astype(np.float64) for s in states], v.astype(np.float64),
+                              steps)
+    e = max_rel_energy(hist, ohist, ("energy", "norm2"), floor=1.0)
+    st = max(_rel(lat.get_state(i), ostates[i]) for i in range(nstates))
+    if prec == "fp64":
+        assert e <= 1e-10 and st <= 1e-10, (e, st)
+    else:
+        check(f"fdtd.many_states[{n},{nstates}].energies", e, 1.7e-7)
+        check(f"fdtd.many_states[{n},{nstates}].states", st, 1.5e-6)
+    lat.close()
+
+
 @pytest.mark.parametrize("n,prec,center,moments", [
     (16, "fp64", "cell", True), (32, "fp32", "origin", False), (96, "fp32", "cell", True),
     (128, "fp64", "origin", False),
