@@ -26,7 +26,7 @@ struct NVariants<float, 64> {
 };
 template <>
 struct NVariants<float, 96> {
-    static constexpr int value = 3;
+    static constexpr int value = 4;
 };
 template <>
 struct NVariants<float, 128> {

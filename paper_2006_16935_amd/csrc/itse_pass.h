@@ -117,6 +117,7 @@ ITSE_PLAN(float, 64, 1, 1, 4, 16, 4)
 ITSE_PLAN(float, 64, 2, 2, 4, 16, 4)
 ITSE_PLAN(float, 96, 1, 1, 4, 16, 4)
 ITSE_PLAN(float, 96, 2, 2, 4, 16, 4)
+ITSE_PLAN(float, 96, 3, 2, 3, 16, 4)
 ITSE_PLAN(float, 128, 0, 1, 8, 16, 2)
 ITSE_PLAN(float, 128, 1, 2, 4, 16, 4)
 ITSE_PLAN(float, 192, 0, 2, 8, 16, 8)

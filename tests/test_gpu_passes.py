@@ -18,7 +18,7 @@ from measure import check, max_rel_energy
 pytestmark = pytest.mark.gpu
 
 CASES = [(32, "fp32", 1), (48, "fp32", 1), (48, "fp32", 2), (64, "fp32", 1), (64, "fp32", 2), (96, "fp32", 1),
-         (96, "fp32", 2),
+         (96, "fp32", 2), (96, "fp32", 3),
          (48, "fp64", 0), (96, "fp64", 0), (128, "fp32", 0), (128, "fp32", 1), (128, "fp64", 0),
          (192, "fp32", 0), (192, "fp64", 0), (256, "fp32", 0), (256, "fp32", 1), (256, "fp32", 2), (256, "fp32", 3),
          (256, "fp32", 4), (256, "fp32", 5),
