@@ -14,7 +14,7 @@ struct NVariants {
 };
 template <>
 struct NVariants<float, 32> {
-    static constexpr int value = 2;
+    static constexpr int value = 3;
 };
 template <>
 struct NVariants<float, 48> {

@@ -109,8 +109,12 @@ ITSE_PLAN(float, 64, 0, 1, 4, 16, 1)
 ITSE_PLAN(float, 96, 0, 1, 4, 16, 2)
 // the batch sizes: column workgroups of four waves (one kz chunk of W = 20 at
 // N = 32: the whole half row), and the y axis split in two (twice the plane
-// workgroups, for batches of few lattices)
+// workgroups, for batches of few lattices).  N = 32 variant 2 and N = 96 variant
+// 3: plane workgroups of two and three waves, so that each wave owns a whole
+// number of 64-lane rounds of four-value chunks (64 and 192 chunks; four waves
+// own 32 and 144)
 ITSE_PLAN(float, 32, 1, 1, 4, 20, 4)
+ITSE_PLAN(float, 32, 2, 1, 2, 20, 4)
 ITSE_PLAN(float, 48, 1, 1, 4, 16, 4)
 ITSE_PLAN(float, 48, 2, 2, 4, 16, 4)
 ITSE_PLAN(float, 64, 1, 1, 4, 16, 4)

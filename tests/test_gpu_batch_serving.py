@@ -63,11 +63,12 @@ def test_batched_mix_matches_oracle_and_alone(itse, orc):
         lat.close()
 
 
-@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_batched_mix_under_other_schedules(itse, orc, variant):
     """The batched-form mix under the other schedules of the batch sizes (column
-    workgroups of four waves; the y axis split in two where the size has it): the
-    batch equals each lattice stepped alone bitwise, and the energies follow the
+    workgroups of four waves; the y axis split in two where the size has it; plane
+    workgroups of two or three waves, each owning whole update rounds): the batch
+    equals each lattice stepped alone bitwise, and the energies follow the
     oracle."""
     probs = synth.batch_problems(count=8, seed=5, nstates=2)
     for n in (32, 48, 64, 96):

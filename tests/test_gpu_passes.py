@@ -17,8 +17,8 @@ from measure import check, max_rel_energy
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(32, "fp32", 1), (48, "fp32", 1), (48, "fp32", 2), (64, "fp32", 1), (64, "fp32", 2), (96, "fp32", 1),
-         (96, "fp32", 2), (96, "fp32", 3),
+CASES = [(32, "fp32", 1), (32, "fp32", 2), (48, "fp32", 1), (48, "fp32", 2),
+         (64, "fp32", 1), (64, "fp32", 2), (96, "fp32", 1), (96, "fp32", 2), (96, "fp32", 3),
          (48, "fp64", 0), (96, "fp64", 0), (128, "fp32", 0), (128, "fp32", 1), (128, "fp64", 0),
          (192, "fp32", 0), (192, "fp64", 0), (256, "fp32", 0), (256, "fp32", 1), (256, "fp32", 2), (256, "fp32", 3),
          (256, "fp32", 4), (256, "fp32", 5),
@@ -106,7 +106,8 @@ def test_kinetic_schedules(itse, orc, n, prec, variant, kin):
 
 @pytest.mark.parametrize("n,prec,variant", [(96, "fp64", 0), (128, "fp64", 0), (128, "fp32", 1),
                                             (192, "fp32", 0), (256, "fp64", 0), (256, "fp64", 1),
-                                            (48, "fp32", 2), (64, "fp32", 1), (96, "fp32", 2), (256, "fp32", 5)])
+                                            (48, "fp32", 2), (64, "fp32", 1), (96, "fp32", 2), (256, "fp32", 5),
+                                            (32, "fp32", 2), (96, "fp32", 3)])
 def test_multistate_steps_large(itse, orc, n, prec, variant):
     """Three states (even, odd, odd deflated against the odd one), Cornell potential,
     a few steps: every step's energies and the final states match the oracle."""
