@@ -1253,7 +1253,9 @@ k_plane_inv(const JobRef *__restrict__ jobs, int mode) {
 // of one job; it marches along x.  Each thread owns one 16-byte vector of VL
 // consecutive z in the tile's plane; its values at x - 1, x, x + 1 stay in
 // registers, the plane x with one halo row on each side goes through LDS for the
-// y and z neighbours.  Every load is issued one plane ahead of its use.
+// y and z neighbours.  The halo rows and V are loaded one iteration before their
+// use; the centre rows one iteration before their use up to three states, and in
+// the iteration of their use with more (see AHEAD below).
 // ---------------------------------------------------------------------------
 constexpr int fd_rows(int n, int gpr) {
     int best = 1;
@@ -1352,7 +1354,8 @@ __global__ void __launch_bounds__(NT) k_fdtd(const JobRef *__restrict__ jobs, in
     const bool hin = hal && hy >= 0 && hy < N;
     auto off = [&](int xx, int yy, int zz) { return ((size_t)xx * N + yy) * N + zz; };
     // the planes before the first and after the last are outside the box for
-    // x0 = 0 and x0 + XS = N, else real planes of the lattice
+    // x0 = 0 and x0 + XS = N, else real planes of the lattice.
+    //
     // Instances of up to three states load the centre rows two planes ahead (plane
     // xx + 2 in iteration xx, combined after the stencil, so that the loads' latency
     // overlaps it).  With four or more the raw loads held across the stencil cost a
