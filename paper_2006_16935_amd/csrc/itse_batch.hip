@@ -383,9 +383,12 @@ static itse_status time_variant(int n, int precision, int v, int nstates, void *
     if (!st && count > 1) st = itse_batch_create(count, lats.data(), stream, &B);
     auto steps = [&](int k) { return B ? itse_batch_step(B, k) : itse_step(lats[0], k, nullptr); };
     if (!st) st = steps(3);
-    const int reps = n >= 192 ? 10 : 30;
+    // steps per trial, and the fastest of three trials: the schedules of a size can
+    // lie within a percent of each other (host-side setup of the lattices costs
+    // more than these steps)
+    const int reps = n >= 192 ? 30 : 60;
     float ms = 1e30f;
-    for (int trial = 0; trial < 2 && !st; ++trial) {
+    for (int trial = 0; trial < 3 && !st; ++trial) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         hipError_t he = hipEventCreate(&e0);
         if (he == hipSuccess) he = hipEventCreate(&e1);
