@@ -325,9 +325,9 @@ itse_status itse_batch_destroy(itse_batch *b);
  * lattice stepped alone).  Takes FP32 transform lattices of real states with N in
  * {32, 48, 64, 96} created under a schedule variant whose plane and column
  * workgroups have 256 threads (1 at each of these N, 2 at N = 48, 64 and 96), at
- * most two states, in at
- * most eight groups of equal (N, schedule); otherwise ITSE_EINVAL.  Steps whose options need position moments or
- * projections of states along different axes take the graph path.  on = 0
+ * most two states, in at most eight groups of equal (N, schedule); otherwise
+ * ITSE_EINVAL.  Steps whose options need position moments or projections of
+ * states along different axes take the graph path.  on = 0
  * returns to graph replay (the default, and the faster path on MI355X: each
  * grid-wide barrier there costs tens of microseconds, several per step). */
 itse_status itse_batch_set_persistent(itse_batch *b, int on);
